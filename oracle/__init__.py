@@ -1,0 +1,218 @@
+"""CPU oracle for the SLIC superpixel path: numpy front end to ``slic_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+the benchmark's CPU-baseline leg may import this module.  It shares no code
+with the GPU library.  Each function names the passage of the paper (gSLICr,
+arXiv 1509.04232) that it follows; the C source states the readings taken
+where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRCS = [os.path.join(_HERE, "slic_oracle.c")]
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Flags that make the oracle's FP32 evaluation order the one written in the
+# source: no contraction into FMA, no fast-math reassociation.
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, *_SRCS, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_F = ctypes.c_float
+_D = ctypes.c_double
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    sig = {
+        "orc_grid": [_I, _I, _I, _I, _P, _P, _P],
+        "orc_rgb_to_lab": [_P, _I, _I, _I, _I, _P, _P, _P],
+        "orc_seed": [_P, _P, _P, _I, _I, _I, _I, _P],
+        "orc_assign": [_P, _P, _P, _I, _I, _I, _F, _P, _P],
+        "orc_update": [_P, _P, _P, _I, _I, _P, _I, _P, _P],
+        "orc_kmeans": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _P, _P, _P],
+        "orc_energy": [_P, _P, _P, _I, _I, _I, _F, _P, _I, _P, _P],
+        "orc_connectivity": [_P, _I, _I, _I, _I, _P, _P, _P],
+        "orc_lab_tables": [_P, _P],
+        "orc_gradient_at": [_P, _P, _P, _I, _I, _I, _I],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.orc_lab_tables.restype = None
+    lib.orc_gradient_at.restype = ctypes.c_float
+    lib.orc_cbrt_export.argtypes = [_D]
+    lib.orc_cbrt_export.restype = _D
+    lib.orc_weight.argtypes = [_F, _I]
+    lib.orc_weight.restype = _F
+    lib.orc_qshift.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def qshift() -> int:
+    """Fixed-point scale exponent of the colour values in the centre sums."""
+    return int(_load().orc_qshift())
+
+
+def grid(width: int, height: int, S: int = 0, K: int = 0):
+    """(S, ns_c, ns_r): Section 2's grid interval and Section 3's ns_r x ns_c map."""
+    out = [ctypes.c_int32() for _ in range(3)]
+    _check(_load().orc_grid(width, height, S, K, *[ctypes.byref(o) for o in out]), "grid")
+    return tuple(int(o.value) for o in out)
+
+
+def cbrt(t: float) -> float:
+    """The oracle's Newton cube root (FP64)."""
+    return float(_load().orc_cbrt_export(float(t)))
+
+
+def lab_tables():
+    lin = np.empty(256, np.float32)
+    nm = np.empty(9, np.float32)
+    _load().orc_lab_tables(_ptr(lin), _ptr(nm))
+    return lin, nm.reshape(3, 3)
+
+
+def rgb_to_lab(rgb: np.ndarray, pitch: int | None = None):
+    """Section 3, image space conversion.  ``rgb``: uint8 (H, W, C), C in {3, 4},
+    or a flat byte buffer with ``pitch``.  Returns planar float32 (L, a, b),
+    each (H, W)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    h, w, c = rgb.shape
+    if pitch is None:
+        pitch = w * c
+    L = np.empty((h, w), np.float32)
+    A = np.empty((h, w), np.float32)
+    B = np.empty((h, w), np.float32)
+    _check(_load().orc_rgb_to_lab(_ptr(rgb), w, h, pitch, c, _ptr(L), _ptr(A), _ptr(B)), "lab")
+    return L, A, B
+
+
+def gradient_at(lab, x: int, y: int) -> float:
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    return float(_load().orc_gradient_at(_ptr(L), _ptr(A), _ptr(B), w, h, x, y))
+
+
+def seed(lab, S: int, perturb: bool):
+    """Section 2 seed perturbation, Section 3 centre initialisation.
+    Returns float32 (K, 5) centres (L, a, b, x, y)."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    _, nc, nr = grid(w, h, S)
+    cen = np.empty((nc * nr, 5), np.float32)
+    _check(_load().orc_seed(_ptr(L), _ptr(A), _ptr(B), w, h, S, int(perturb), _ptr(cen)), "seed")
+    return cen
+
+
+def weight(m: float, S: int) -> float:
+    return float(_load().orc_weight(float(m), S))
+
+
+def assign(lab, S: int, m: float, centres: np.ndarray):
+    """Eq. 1 and Section 3's nine-candidate association.  Returns int32 (H, W)."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    cen = np.ascontiguousarray(centres, np.float32)
+    lab_out = np.empty((h, w), np.int32)
+    _check(_load().orc_assign(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), _ptr(cen),
+                              _ptr(lab_out)), "assign")
+    return lab_out
+
+
+def update(lab, labels: np.ndarray, centres: np.ndarray):
+    """Section 3 centre update.  Returns (new centres (K,5), counts (K,))."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    cen = np.array(centres, np.float32, copy=True, order="C")
+    cnt = np.empty(cen.shape[0], np.int32)
+    lb = np.ascontiguousarray(labels, np.int32)
+    _check(_load().orc_update(_ptr(L), _ptr(A), _ptr(B), w, h, _ptr(lb), cen.shape[0],
+                              _ptr(cen), _ptr(cnt)), "update")
+    return cen, cnt
+
+
+def kmeans(lab, S: int, m: float, perturb: bool, iters: int):
+    """Section 4's loop: seed, associate, iters x (update, associate).
+    Returns (labels (H,W), centres (K,5), counts (K,))."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    _, nc, nr = grid(w, h, S)
+    cen = np.empty((nc * nr, 5), np.float32)
+    cnt = np.empty(nc * nr, np.int32)
+    lb = np.empty((h, w), np.int32)
+    _check(_load().orc_kmeans(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(perturb), iters,
+                              _ptr(cen), _ptr(cnt), _ptr(lb)), "kmeans")
+    return lb, cen, cnt
+
+
+def energy(lab, S: int, m: float, centres: np.ndarray, labels: np.ndarray) -> float:
+    """Mean Eq. 1 distance between each pixel and its associated centre."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    cen = np.ascontiguousarray(centres, np.float32)
+    lb = np.ascontiguousarray(labels, np.int32)
+    out = ctypes.c_double()
+    _check(_load().orc_energy(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), _ptr(cen),
+                              cen.shape[0], _ptr(lb), ctypes.byref(out)), "energy")
+    return float(out.value)
+
+
+def connectivity(labels: np.ndarray, S: int, min_segment: int = 0):
+    """Section 2's connectivity clean-up under the canonical merge rule.
+    Returns (segment labels (H,W), n_segments, seg_cluster (n_segments,))."""
+    lb = np.ascontiguousarray(labels, np.int32)
+    h, w = lb.shape
+    out = np.empty((h, w), np.int32)
+    seg = np.empty(h * w, np.int32)
+    ns = ctypes.c_int32()
+    _check(_load().orc_connectivity(_ptr(lb), w, h, S, min_segment, _ptr(out), ctypes.byref(ns),
+                                    _ptr(seg)), "connectivity")
+    return out, int(ns.value), seg[: ns.value].copy()
+
+
+def segment(rgb: np.ndarray, S: int, m: float, iters: int, perturb: bool = True,
+            connectivity_on: bool = False, min_segment: int = 0):
+    """The whole path of Section 4's listing.  Returns a dict with lab, labels
+    (after the k-means loop), centres, counts, energy and, when
+    ``connectivity_on``, seg_labels / n_segments / seg_cluster."""
+    lab = rgb_to_lab(rgb)
+    labels, cen, cnt = kmeans(lab, S, m, perturb, iters)
+    res = {"lab": lab, "labels": labels, "centres": cen, "counts": cnt,
+           "energy": energy(lab, S, m, cen, labels)}
+    if connectivity_on:
+        seg, ns, sc = connectivity(labels, S, min_segment)
+        res.update(seg_labels=seg, n_segments=ns, seg_cluster=sc)
+    return res
