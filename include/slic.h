@@ -1,0 +1,142 @@
+/*
+ * libslic: SLIC superpixels on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one gSLICr (Ren, Prisacariu and Reid, arXiv 1509.04232)
+ * runs on a GPU: convert the image to CIELAB, place centres on a grid of
+ * step S, perturb them to the lowest-gradient pixel nearby, then alternate
+ * (associate every pixel with the nearest of the nine centres around its
+ * grid cell under Eq. 1's distance; move each centre to the mean of its
+ * pixels), and finally enforce connectivity.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named d_* are device pointers on the current HIP device; the
+ *    caller owns every device buffer (input, outputs, workspace).  A context
+ *    (slic_ctx) owns only its host-side record.
+ *  - `hip_stream` is a hipStream_t (NULL: the null stream).  All device work
+ *    is enqueued on it and nothing synchronises the host, except where an
+ *    entry point says so.
+ *  - Arguments are validated on the host before anything is enqueued; on
+ *    SLIC_EINVAL nothing was enqueued and a context is unchanged.  A failed
+ *    HIP call returns SLIC_EHIP and poisons the context: later calls on it
+ *    return SLIC_ESTATE.  No C++ exception crosses this interface.
+ *  - A context is not thread-safe; distinct contexts are independent but
+ *    must not share a workspace while both are in use.
+ *  - Arithmetic: FP32 in a fixed operation order without contraction, exact
+ *    integer centre sums; results are bit-identical to the CPU reference and
+ *    independent of launch shapes and run-to-run scheduling.
+ */
+#ifndef SLIC_H
+#define SLIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slic_ctx slic_ctx;
+
+enum {
+    SLIC_OK = 0,
+    SLIC_EINVAL = 1, /* invalid argument or workspace too small */
+    SLIC_ENOMEM = 2, /* host allocation failed */
+    SLIC_EHIP = 3,   /* a HIP runtime call failed (no device, launch error, ...) */
+    SLIC_ESTATE = 4  /* call not valid in the context's state, or context poisoned */
+};
+
+enum {
+    SLIC_PERTURB_SEEDS = 1 /* move each seed to the lowest-gradient pixel of its 3x3 window
+                              (Section 2, "perturbed to the lowest gradient position") */
+};
+
+/* The problem statement of Section 2: an image of N = width*height pixels,
+ * the grid interval S (or the desired superpixel count K, S = sqrt(N/K)),
+ * and the compactness m of Eq. 1. */
+typedef struct {
+    int32_t width, height; /* >= 1 each, width*height < 2^31 */
+    int32_t pitch;         /* bytes between input rows, >= width*channels */
+    int32_t channels;      /* 3: R,G,B bytes; 4: R,G,B,x (the paper's 4-byte pixels) */
+    int32_t S;             /* grid step >= 1, or 0 to derive it from K */
+    int32_t K;             /* desired superpixel count, used only when S == 0:
+                              S = max(1, floor(sqrt(N/K) + 0.5)) */
+    float m;               /* compactness, finite and >= 0 */
+    int32_t flags;         /* SLIC_PERTURB_SEEDS or 0 */
+    int32_t min_segment;   /* connectivity: components smaller than this many pixels
+                              are merged; 0: merge when 4*size < S*S */
+} slic_params;
+
+/* Device workspace needed by slic_init / slic_segment for these parameters,
+ * in bytes (pure host computation).  0 if the parameters are invalid. */
+size_t slic_workspace_bytes(const slic_params* p);
+
+/* Grid of Sections 2-3: the integer step S and the ns_c x ns_r map of
+ * centres, ns_c = ceil(width/S), ns_r = ceil(height/S); cluster k of cell
+ * (cx, cy) is k = cy*ns_c + cx.  Pure host; any output pointer may be NULL. */
+int slic_grid(const slic_params* p, int32_t* S, int32_t* ns_c, int32_t* ns_r);
+
+/* Section 4's listing up to the first association: converts d_rgb
+ * (height rows of `pitch` bytes) to CIELAB, seeds the centres (Section 3,
+ * cluster centre initialisation) and associates every pixel once.  On
+ * success *out receives a new context bound to the workspace, the stream and
+ * the current device.  d_rgb may be reused once this work has completed on
+ * the stream.  d_ws must be 256-byte aligned, ws_bytes >=
+ * slic_workspace_bytes(p). */
+int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* hip_stream,
+              void* d_ws, size_t ws_bytes);
+
+/* n_iters >= 0 rounds of (update every centre to the mean of its pixels;
+ * associate every pixel), the loop body of Section 4's listing.
+ * slic_iterate(c, a) followed by slic_iterate(c, b) equals
+ * slic_iterate(c, a + b).  SLIC_ESTATE after slic_enforce_connectivity. */
+int slic_iterate(slic_ctx* ctx, int32_t n_iters);
+
+/* Connectivity clean-up (Section 2, last step): relabels the context's
+ * label map in place into 4-connected segments, merging every segment below
+ * the size threshold (slic_params.min_segment) into the segment left of
+ * (or, at a row start, above) its first pixel; segments are numbered 0..
+ * in raster order of their first pixel.  *d_n_segments (device int32, may
+ * be NULL) receives their count.  Afterwards slic_iterate returns
+ * SLIC_ESTATE; the centres stay those of the last association. */
+int slic_enforce_connectivity(slic_ctx* ctx, int32_t* d_n_segments);
+
+/* Copies of the context's state (device to device, on the context's
+ * stream).  Labels: int32[height*width], row-major.  Centres: float[K][5]
+ * = (L, a, b, x, y) as used by the last association; counts: int32[K]
+ * pixels per centre at the last update (0 before any update), may be NULL.
+ * Lab: three planar float[height*width] arrays. */
+int slic_get_labels(const slic_ctx* ctx, int32_t* d_labels);
+int slic_get_centres(const slic_ctx* ctx, float* d_centres, int32_t* d_counts);
+int slic_get_lab(const slic_ctx* ctx, float* d_L, float* d_a, float* d_b);
+
+/* Energy: the mean over pixels of Eq. 1's D_s between each pixel and the
+ * centre it is associated with (double, written to *d_out).  Deterministic.
+ * SLIC_ESTATE after slic_enforce_connectivity. */
+int slic_energy(const slic_ctx* ctx, double* d_out);
+
+/* The whole of Section 4's listing in one call: init, n_iters rounds,
+ * optionally the energy (d_energy != NULL, taken before connectivity),
+ * optionally connectivity (enforce != 0).  Outputs: d_labels int32[H*W]
+ * (required), d_centres float[K][5] (may be NULL), d_n_segments int32 (may
+ * be NULL; written only when enforce != 0). */
+int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, int32_t enforce,
+                 int32_t* d_labels, float* d_centres, double* d_energy, int32_t* d_n_segments,
+                 void* hip_stream, void* d_ws, size_t ws_bytes);
+
+void slic_destroy(slic_ctx* ctx);
+const char* slic_strerror(int code);
+
+/* Kernel timing for measurement.  While enabled (library-wide), every
+ * kernel launch of the library is bracketed by HIP events recorded on the
+ * stream it is launched on.  slic_timing_read synchronises on the recorded
+ * events, returns the summed duration in milliseconds and the launch count
+ * of the kernels whose name starts with `kernel_prefix` (NULL: all), and
+ * forgets them.  Not for concurrent use from several host threads. */
+int slic_timing_enable(int32_t on);
+int slic_timing_read(const char* kernel_prefix, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLIC_H */

@@ -73,22 +73,26 @@ int orc_grid(int32_t w, int32_t h, int32_t S_in, int32_t K_in, int32_t* S_out,
 
 /* Cube root by Newton's method on y^3 = t, t > 0 and normal.  t = f*2^e with
  * f in [0.5,1); e is shifted to a multiple of three so that g = f*2^r lies in
- * [0.5,4); a linear seed on that interval has relative error below 8%, and
- * each step y <- (2y + g/y^2)/3 squares the error, so six steps reach the
- * double-precision fixed point.  cbrt(1) is exactly 1. */
+ * [0.5,4) and cbrt(t) = cbrt(g)*2^q.  A quadratic seed on that interval has
+ * relative error below 1.7%; each step y <- (2y^3 + g)/(3y^2) squares the
+ * error, so four steps reach the double-precision fixed point (within two
+ * ulps of the true root).  cbrt(1) is exactly 1. */
 static double orc_cbrt(double t) {
     int e;
     double f = frexp(t, &e);
     int r = ((e % 3) + 3) % 3;
     double g = ldexp(f, r);
     int q = (e - r) / 3;
-    double y = 0.7 + 0.23 * g;
-    for (int i = 0; i < 6; i++) {
+    double lin = 0.6052 + 0.4255 * g;
+    double g2 = g * g;
+    double y = lin - 0.04658 * g2;
+    for (int i = 0; i < 4; i++) {
         double y2 = y * y;
-        double quo = g / y2;
-        double two_y = 2.0 * y;
-        double s = two_y + quo;
-        y = s / 3.0;
+        double y3 = y2 * y;
+        double num = 2.0 * y3;
+        num = num + g;
+        double den = 3.0 * y2;
+        y = num / den;
     }
     return ldexp(y, q);
 }
