@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the SLIC superpixel path on one MI355X.
+
+One step = one frame through slic_segment: CIELAB conversion, seeding with
+3x3 gradient perturbation, association, `iters` rounds of (centre update,
+association), and connectivity enforcement, on a synthetic image already
+resident in HBM.  Prints ONE JSON line (rank 0, one GPU):
+
+  value       frames/s of the headline workload (c2: 640x480, S=16, m=10,
+              10 iterations, perturbed seeds, connectivity)
+  roofline    the dominant kernel (the fused association + accumulation):
+              algorithmic bytes per launch / its average launch duration,
+              measured with HIP events on the launch stream
+  cpu_baseline the CPU oracle (single thread) on a bounded sample of frames
+  extra       Mpix/s per iteration at 640x480 and 1920x1080, per-kernel
+              times, the 1080p frame rate
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "frames/s & Mpix/s/iter at 640x480 and 1080p; learned vs plain at equal energy"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_c2_traffic.json")
+ASSIGN_SRC = os.path.join(ROOT, "paper_1509_04232_amd", "csrc", "assign.hip")
+
+
+def assign_bytes(n_pixels: int, n_clusters: int) -> int:
+    """Algorithmic bytes of one association launch: read Lab (12 B/pixel),
+    write the label (4 B/pixel), read each centre (20 B) and add its five
+    sums and count (48 B)."""
+    return 16 * n_pixels + 68 * n_clusters
+
+
+class Frame:
+    """Preallocated buffers for repeated slic_segment calls on one image."""
+
+    def __init__(self, slic, wl, device):
+        import numpy as np  # noqa: F401
+        import torch
+
+        import synth
+        self.slic = slic
+        self.wl = wl
+        img = synth.image_for(wl)
+        self.rgb = torch.from_numpy(img.reshape(-1)).to(device)
+        self.p = slic.Params(wl.width, wl.height, S=wl.S, m=wl.m, perturb=wl.perturb,
+                             min_segment=wl.min_segment)
+        self.cp = self.p.c()
+        self.ws = slic.workspace_for(self.p, device)
+        self.labels = torch.empty((wl.height, wl.width), dtype=torch.int32, device=device)
+        self.nseg = torch.empty(1, dtype=torch.int32, device=device)
+        self.stream = torch.cuda.current_stream().cuda_stream
+        self.K = self.p.n_clusters
+
+    def run(self, iters: int, enforce: bool) -> None:
+        self.slic.slic_segment(self.cp, self.rgb.data_ptr(), iters, 1 if enforce else 0,
+                               self.labels.data_ptr(), None, None,
+                               self.nseg.data_ptr() if enforce else None, self.stream,
+                               self.ws.data_ptr(), self.ws.numel())
+
+
+def time_frames(torch, frame: Frame, steps: int, warmup: int, iters: int, enforce: bool) -> float:
+    """Seconds per frame over `steps` timed frames."""
+    for _ in range(warmup):
+        frame.run(iters, enforce)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        frame.run(iters, enforce)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+KERNELS = ("lab", "seed", "assign", "finalize", "ccl_", "energy")
+
+
+def kernel_times(slic, torch, frame: Frame, steps: int, iters: int, enforce: bool):
+    """Per-kernel average launch durations (ms) with HIP events recorded on
+    the launch stream, over `steps` frames."""
+    slic.slic_timing_enable(True)
+    try:
+        for _ in range(steps):
+            frame.run(iters, enforce)
+        torch.cuda.synchronize()
+    finally:
+        slic.slic_timing_enable(False)
+    out = {}
+    for name in KERNELS:
+        total, n = slic.slic_timing_read(name)
+        if n:
+            out[name] = {"avg_ms": total / n, "launches_per_frame": n / steps}
+    return out
+
+
+def traffic_from_profile():
+    """HBM bytes per association launch from the committed PMC summary, or
+    None if it is missing or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        src = hashlib.sha256(open(ASSIGN_SRC, "rb").read()).hexdigest()
+        if t.get("assign_src_sha256") != src:
+            return None
+        return t.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, seconds: float):
+    import oracle
+    import synth
+    img = synth.image_for(wl)
+    oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, wl.connectivity, wl.min_segment)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, wl.connectivity, wl.min_segment)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} frames of {wl.name} ({wl.width}x{wl.height}, {wl.iters} iterations, "
+                      f"connectivity), single-threaded oracle on {platform.processor() or 'host'}"
+                      f" ({os.cpu_count()} logical CPUs visible)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run a plain device copy of this many bytes (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the SLIC path has no multi-GPU mode "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1509_04232_amd as slic
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = synth.WORKLOADS["c2"]
+    frame = Frame(slic, wl, dev)
+    sec = time_frames(torch, frame, args.steps, args.warmup, wl.iters, wl.connectivity)
+    value = 1.0 / sec
+
+    ktimes = kernel_times(slic, torch, frame, min(args.steps, 200), wl.iters, wl.connectivity)
+    a_ms = ktimes["assign"]["avg_ms"]
+    nbytes = assign_bytes(wl.n_pixels, frame.K)
+    achieved = nbytes / (a_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic_from_profile(), "kernel": "assign_kernel",
+                "bytes_per_launch": nbytes, "avg_launch_us": round(a_ms * 1e3, 3)}
+
+    extra = {"kernels_c2": {k: {"avg_us": round(v["avg_ms"] * 1e3, 3),
+                                "per_frame": v["launches_per_frame"]} for k, v in ktimes.items()}}
+    if not args.no_extra:
+        for name in ("c2", "c3"):
+            w = synth.WORKLOADS[name]
+            f = frame if name == "c2" else Frame(slic, w, dev)
+            steps = max(20, args.steps // (1 if name == "c2" else 5))
+            t10 = time_frames(torch, f, steps, 5, 10, False)
+            t0 = time_frames(torch, f, steps, 5, 0, False)
+            t_iter = (t10 - t0) / 10
+            entry = {"mpix_per_s_per_iter": round(w.n_pixels / t_iter / 1e6, 1),
+                     "us_per_iter": round(t_iter * 1e6, 3)}
+            if name != "c2":
+                tf = time_frames(torch, f, steps, 5, w.iters, w.connectivity)
+                entry["frames_per_s"] = round(1.0 / tf, 1)
+                kt = kernel_times(slic, torch, f, 20, w.iters, w.connectivity)
+                a = kt["assign"]["avg_ms"]
+                b = assign_bytes(w.n_pixels, f.K)
+                entry["assign_avg_us"] = round(a * 1e3, 3)
+                entry["assign_gbps"] = round(b / (a * 1e-3) / 1e9, 1)
+                entry["assign_hbm_frac"] = round(b / (a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+            extra[name] = entry
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: one 640x480 seeded Voronoi image (256 regions, sigma 8), "
+                               "S=16 (K=1200), m=10, 10 iterations, perturbed seeds, "
+                               "connectivity (S*S/4 merge)",
+                   "global_batch": 1, "parallelism": "none (one GPU)"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    line["extra"] = extra
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -126,12 +126,14 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
 void slic_destroy(slic_ctx* ctx);
 const char* slic_strerror(int code);
 
-/* Kernel timing for measurement.  While enabled (library-wide), every
- * kernel launch of the library is bracketed by HIP events recorded on the
- * stream it is launched on.  slic_timing_read synchronises on the recorded
- * events, returns the summed duration in milliseconds and the launch count
- * of the kernels whose name starts with `kernel_prefix` (NULL: all), and
- * forgets them.  Not for concurrent use from several host threads. */
+/* Kernel timing for measurement.  slic_timing_enable(1) forgets earlier
+ * records and starts recording: every kernel launch of the library is then
+ * bracketed by HIP events on the stream it is launched on.
+ * slic_timing_enable(0) stops recording and keeps the records.
+ * slic_timing_read synchronises on the recorded events and returns the
+ * summed duration in milliseconds and the launch count of the kernels whose
+ * name starts with `kernel_prefix` (NULL: all).  Not for concurrent use from
+ * several host threads. */
 int slic_timing_enable(int32_t on);
 int slic_timing_read(const char* kernel_prefix, double* total_ms, int64_t* launches);
 

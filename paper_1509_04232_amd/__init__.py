@@ -1,0 +1,146 @@
+"""SLIC superpixels (gSLICr, arXiv 1509.04232) on one AMD Instinct MI355X.
+
+The work runs in libslic's hand-written HIP kernels behind the C ABI of
+``include/slic.h``; this package only marshals torch tensors (device memory)
+and the current torch stream into those calls.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import _abi
+from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, SLIC_OK,
+                   SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_destroy,
+                   slic_enforce_connectivity, slic_energy, slic_get_centres, slic_get_lab,
+                   slic_get_labels, slic_grid, slic_init, slic_iterate, slic_segment,
+                   slic_strerror, slic_timing_enable, slic_timing_read, slic_workspace_bytes)
+
+__all__ = [
+    "Params", "Context", "segment", "workspace_for", "SlicError", "SlicParams", *EXPORTED,
+]
+
+
+@dataclasses.dataclass
+class Params:
+    """Section 2's problem statement: image size, S (or K), compactness m."""
+    width: int
+    height: int
+    S: int = 0
+    K: int = 0
+    m: float = 10.0
+    perturb: bool = True
+    min_segment: int = 0
+    channels: int = 3
+    pitch: int | None = None
+
+    def c(self) -> SlicParams:
+        return SlicParams(self.width, self.height,
+                          self.pitch if self.pitch is not None else self.width * self.channels,
+                          self.channels, self.S, self.K, float(self.m),
+                          SLIC_PERTURB_SEEDS if self.perturb else 0, self.min_segment)
+
+    def grid(self):
+        return slic_grid(self.c())
+
+    @property
+    def n_clusters(self) -> int:
+        _, nc, nr = self.grid()
+        return nc * nr
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check_rgb(rgb: torch.Tensor, p: Params) -> None:
+    if rgb.device.type != "cuda" or rgb.dtype != torch.uint8:
+        raise ValueError("rgb must be a uint8 tensor on the GPU")
+    pitch = p.pitch if p.pitch is not None else p.width * p.channels
+    if not rgb.is_contiguous() or rgb.numel() < (p.height - 1) * pitch + p.width * p.channels:
+        raise ValueError("rgb must be contiguous and hold height rows of `pitch` bytes")
+
+
+def workspace_for(p: Params, device=None) -> torch.Tensor:
+    n = slic_workspace_bytes(p.c())
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+class Context:
+    """A slic_ctx: slic_init on construction, then iterate / enforce / get."""
+
+    def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None):
+        _check_rgb(rgb, p)
+        self.params = p
+        self._cp = p.c()
+        self.stream = stream
+        self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
+        self._rgb = rgb  # kept alive until the conversion has run
+        self.ctx = slic_init(self._cp, rgb.data_ptr(), _stream(stream), self.ws.data_ptr(),
+                             self.ws.numel())
+        self.device = rgb.device
+
+    def iterate(self, n: int) -> "Context":
+        slic_iterate(self.ctx, n)
+        return self
+
+    def enforce_connectivity(self) -> torch.Tensor:
+        n = torch.empty(1, dtype=torch.int32, device=self.device)
+        slic_enforce_connectivity(self.ctx, n.data_ptr())
+        return n
+
+    def labels(self) -> torch.Tensor:
+        out = torch.empty((self.params.height, self.params.width), dtype=torch.int32,
+                          device=self.device)
+        slic_get_labels(self.ctx, out.data_ptr())
+        return out
+
+    def centres(self):
+        K = self.params.n_clusters
+        cen = torch.empty((K, 5), dtype=torch.float32, device=self.device)
+        cnt = torch.empty(K, dtype=torch.int32, device=self.device)
+        slic_get_centres(self.ctx, cen.data_ptr(), cnt.data_ptr())
+        return cen, cnt
+
+    def lab(self):
+        shape = (self.params.height, self.params.width)
+        out = [torch.empty(shape, dtype=torch.float32, device=self.device) for _ in range(3)]
+        slic_get_lab(self.ctx, *[t.data_ptr() for t in out])
+        return tuple(out)
+
+    def energy(self) -> torch.Tensor:
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        slic_energy(self.ctx, e.data_ptr())
+        return e
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            slic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+
+def segment(rgb: torch.Tensor, p: Params, iters: int, enforce: bool = False,
+            want_centres: bool = False, want_energy: bool = False, stream=None, workspace=None):
+    """slic_segment: the whole listing in one call.  Returns a dict of device
+    tensors: labels (H, W) int32, and optionally centres (K, 5), energy (1,)
+    float64 and n_segments (1,) int32."""
+    _check_rgb(rgb, p)
+    dev = rgb.device
+    ws = workspace if workspace is not None else workspace_for(p, dev)
+    out = {"labels": torch.empty((p.height, p.width), dtype=torch.int32, device=dev)}
+    if want_centres:
+        out["centres"] = torch.empty((p.n_clusters, 5), dtype=torch.float32, device=dev)
+    if want_energy:
+        out["energy"] = torch.empty(1, dtype=torch.float64, device=dev)
+    if enforce:
+        out["n_segments"] = torch.empty(1, dtype=torch.int32, device=dev)
+    ptr = lambda k: out[k].data_ptr() if k in out else None  # noqa: E731
+    slic_segment(p.c(), rgb.data_ptr(), iters, 1 if enforce else 0, out["labels"].data_ptr(),
+                 ptr("centres"), ptr("energy"), ptr("n_segments"), _stream(stream), ws.data_ptr(),
+                 ws.numel())
+    return out

@@ -1,0 +1,142 @@
+"""ctypes binding of libslic's C ABI (``include/slic.h``).
+
+Argument marshalling only: every function here forwards to the library of
+the same name and raises :class:`SlicError` on a non-zero status.  There is
+no fallback: importing this module fails if ``libslic.so`` is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libslic.so")
+
+SLIC_OK, SLIC_EINVAL, SLIC_ENOMEM, SLIC_EHIP, SLIC_ESTATE = 0, 1, 2, 3, 4
+SLIC_PERTURB_SEEDS = 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (hipcc for gfx950) first")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class SlicParams(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int32),
+        ("channels", ctypes.c_int32), ("S", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("m", ctypes.c_float), ("flags", ctypes.c_int32), ("min_segment", ctypes.c_int32),
+    ]
+
+
+class SlicError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib.slic_strerror(code).decode()} (code {code})")
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_PP = ctypes.POINTER(SlicParams)
+
+_SIGS = {
+    "slic_workspace_bytes": ([_PP], ctypes.c_size_t),
+    "slic_grid": ([_PP, _P, _P, _P], ctypes.c_int),
+    "slic_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_iterate": ([_P, _I], ctypes.c_int),
+    "slic_enforce_connectivity": ([_P, _P], ctypes.c_int),
+    "slic_get_labels": ([_P, _P], ctypes.c_int),
+    "slic_get_centres": ([_P, _P, _P], ctypes.c_int),
+    "slic_get_lab": ([_P, _P, _P, _P], ctypes.c_int),
+    "slic_energy": ([_P, _P], ctypes.c_int),
+    "slic_segment": ([_PP, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_destroy": ([_P], None),
+    "slic_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "slic_timing_enable": ([_I], ctypes.c_int),
+    "slic_timing_read": ([ctypes.c_char_p, _P, _P], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != SLIC_OK:
+        raise SlicError(rc, where)
+
+
+def slic_workspace_bytes(p: SlicParams) -> int:
+    n = lib.slic_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise SlicError(SLIC_EINVAL, "slic_workspace_bytes")
+    return int(n)
+
+
+def slic_grid(p: SlicParams):
+    out = [ctypes.c_int32() for _ in range(3)]
+    _check(lib.slic_grid(ctypes.byref(p), *[ctypes.byref(o) for o in out]), "slic_grid")
+    return tuple(int(o.value) for o in out)
+
+
+def slic_init(p: SlicParams, d_rgb: int, stream: int, d_ws: int, ws_bytes: int) -> int:
+    ctx = _P()
+    _check(lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), d_rgb, stream, d_ws, ws_bytes),
+           "slic_init")
+    return int(ctx.value)
+
+
+def slic_iterate(ctx: int, n_iters: int) -> None:
+    _check(lib.slic_iterate(ctx, n_iters), "slic_iterate")
+
+
+def slic_enforce_connectivity(ctx: int, d_n_segments: int | None) -> None:
+    _check(lib.slic_enforce_connectivity(ctx, d_n_segments), "slic_enforce_connectivity")
+
+
+def slic_get_labels(ctx: int, d_labels: int) -> None:
+    _check(lib.slic_get_labels(ctx, d_labels), "slic_get_labels")
+
+
+def slic_get_centres(ctx: int, d_centres: int, d_counts: int | None) -> None:
+    _check(lib.slic_get_centres(ctx, d_centres, d_counts), "slic_get_centres")
+
+
+def slic_get_lab(ctx: int, d_L: int, d_a: int, d_b: int) -> None:
+    _check(lib.slic_get_lab(ctx, d_L, d_a, d_b), "slic_get_lab")
+
+
+def slic_energy(ctx: int, d_out: int) -> None:
+    _check(lib.slic_energy(ctx, d_out), "slic_energy")
+
+
+def slic_segment(p: SlicParams, d_rgb: int, n_iters: int, enforce: int, d_labels: int,
+                 d_centres: int | None, d_energy: int | None, d_n_segments: int | None,
+                 stream: int, d_ws: int, ws_bytes: int) -> None:
+    _check(lib.slic_segment(ctypes.byref(p), d_rgb, n_iters, enforce, d_labels, d_centres,
+                            d_energy, d_n_segments, stream, d_ws, ws_bytes), "slic_segment")
+
+
+def slic_destroy(ctx: int) -> None:
+    lib.slic_destroy(ctx)
+
+
+def slic_strerror(code: int) -> str:
+    return lib.slic_strerror(code).decode()
+
+
+def slic_timing_enable(on: bool) -> None:
+    _check(lib.slic_timing_enable(1 if on else 0), "slic_timing_enable")
+
+
+def slic_timing_read(prefix: str | None = None):
+    """(total milliseconds, launch count) of the recorded kernels matching
+    prefix (records are kept until the next slic_timing_enable(True))."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.slic_timing_read(prefix.encode() if prefix else None, ctypes.byref(ms),
+                                ctypes.byref(n)), "slic_timing_read")
+    return float(ms.value), int(n.value)

@@ -1,0 +1,363 @@
+// The C ABI of libslic: validation, workspace layout, contexts and the
+// control flow of Section 4's listing (convert, initialise the centres,
+// associate, then n x (update, associate), then optionally enforce
+// connectivity), all enqueued on the caller's stream.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "slic_internal.h"
+
+namespace slic {
+
+// ---------------------------------------------------------------- timing
+
+namespace {
+struct TimedLaunch {
+    const char* name;
+    hipEvent_t start, stop;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_launches;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing; }
+
+KernelTimer::KernelTimer(const char* name, hipStream_t s) : name_(name), s_(s), start_(nullptr) {
+    if (!g_timing) return;
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) start_ = e;
+}
+
+KernelTimer::~KernelTimer() {
+    if (!start_) return;
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s_) == hipSuccess)
+        g_launches.push_back({name_, static_cast<hipEvent_t>(start_), e});
+}
+
+// ------------------------------------------------------------- workspace
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int energy_blocks_for(int n) { return (n + 255) / 256; }
+}  // namespace
+
+size_t workspace_layout(int32_t width, int32_t height, const Grid& g, Workspace* ws, char* base) {
+    const size_t n = static_cast<size_t>(width) * height;
+    const size_t K = static_cast<size_t>(g.K);
+    const int nscan = scan_tiles_for(static_cast<int>(n));
+    const int nenergy = energy_blocks_for(static_cast<int>(n));
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    Workspace w{};
+    w.L = reinterpret_cast<float*>(take(n * sizeof(float)));
+    w.A = reinterpret_cast<float*>(take(n * sizeof(float)));
+    w.B = reinterpret_cast<float*>(take(n * sizeof(float)));
+    w.labels = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+    w.cen = reinterpret_cast<float*>(take(K * kCenStride * sizeof(float)));
+    w.counts = reinterpret_cast<int32_t*>(take(K * sizeof(int32_t)));
+    w.sums = reinterpret_cast<long long*>(take(3 * K * kSumStride * sizeof(long long)));
+    w.ccl0 = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+    w.ccl1 = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+    w.ccl2 = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+    w.ccl3 = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
+    w.scan = reinterpret_cast<int32_t*>(take(static_cast<size_t>(nscan) * sizeof(int32_t)));
+    w.partial = reinterpret_cast<double*>(take(static_cast<size_t>(nenergy) * sizeof(double)));
+    w.n_scan_blocks = nscan;
+    w.n_energy_blocks = nenergy;
+    if (ws) *ws = w;
+    return off;
+}
+
+// ------------------------------------------------------------ validation
+
+namespace {
+
+constexpr int32_t kMaxSide = 1 << 24;  // pixel coordinates exact in FP32
+
+// Integer grid step (Section 2: S = sqrt(N/K)), rounded to nearest.
+bool compute_grid(const slic_params* p, Grid* g) {
+    int32_t S = p->S;
+    if (S <= 0) {
+        const double n = static_cast<double>(p->width) * static_cast<double>(p->height);
+        const double s = std::floor(std::sqrt(n / static_cast<double>(p->K)) + 0.5);
+        S = s < 1.0 ? 1 : (s > 2147483647.0 ? 2147483647 : static_cast<int32_t>(s));
+    }
+    g->S = S;
+    g->ns_c = static_cast<int32_t>((static_cast<int64_t>(p->width) + S - 1) / S);
+    g->ns_r = static_cast<int32_t>((static_cast<int64_t>(p->height) + S - 1) / S);
+    g->K = g->ns_c * g->ns_r;
+    g->w = p->m / static_cast<float>(S);
+    return true;
+}
+
+bool params_ok(const slic_params* p) {
+    if (!p) return false;
+    if (p->width < 1 || p->height < 1 || p->width > kMaxSide || p->height > kMaxSide) return false;
+    if (static_cast<int64_t>(p->width) * p->height >= (static_cast<int64_t>(1) << 31) / 2)
+        return false;
+    if (p->channels != 3 && p->channels != 4) return false;
+    if (static_cast<int64_t>(p->pitch) < static_cast<int64_t>(p->width) * p->channels) return false;
+    if (p->S < 0 || (p->S == 0 && p->K < 1)) return false;
+    if (!std::isfinite(p->m) || p->m < 0.0f) return false;
+    if (p->flags & ~SLIC_PERTURB_SEEDS) return false;
+    if (p->min_segment < 0) return false;
+    return true;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+// 0: device memory, SLIC_EINVAL: not device memory, SLIC_EHIP: runtime error
+int check_device_ptr(const void* p) {
+    if (!p) return SLIC_EINVAL;
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof(a));
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e == hipErrorNoDevice || e == hipErrorInsufficientDriver || e == hipErrorNotInitialized) {
+        (void)hipGetLastError();
+        return SLIC_EHIP;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return SLIC_EINVAL;
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) return SLIC_EINVAL;
+    return SLIC_OK;
+}
+
+int check_buffers(const void* rgb, const void* ws) {
+    int rc = check_device_ptr(rgb);
+    if (rc) return rc;
+    return check_device_ptr(ws);
+}
+
+// Section 4's listing up to the first association.
+hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb) {
+    const slic_params& p = c->p;
+    hipError_t e = launch_lab(rgb, p.width, p.height, p.pitch, p.channels, c->ws.L, c->ws.A,
+                              c->ws.B, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch_seed(c->ws, p.width, p.height, c->g, (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0,
+                    c->stream);
+    if (e != hipSuccess) return e;
+    c->t = 0;
+    e = launch_assign(c->ws, p.width, p.height, c->g, c->t, c->ppt, c->stream);
+    if (e == hipSuccess) c->t = 1;
+    return e;
+}
+
+// n rounds of (update, associate): each association launch also completes
+// the previous launch's centre update.
+hipError_t enqueue_iterations(slic_ctx* c, int32_t n) {
+    for (int32_t i = 0; i < n; ++i) {
+        hipError_t e = launch_assign(c->ws, c->p.width, c->p.height, c->g, c->t, c->ppt, c->stream);
+        if (e != hipSuccess) return e;
+        ++c->t;
+    }
+    return hipSuccess;
+}
+
+int fail(slic_ctx* c) {
+    if (c) c->state = 2;
+    return SLIC_EHIP;
+}
+
+}  // namespace
+}  // namespace slic
+
+using namespace slic;
+
+extern "C" {
+
+size_t slic_workspace_bytes(const slic_params* p) {
+    if (!params_ok(p)) return 0;
+    Grid g;
+    compute_grid(p, &g);
+    return workspace_layout(p->width, p->height, g, nullptr, nullptr);
+}
+
+int slic_grid(const slic_params* p, int32_t* S, int32_t* ns_c, int32_t* ns_r) {
+    if (!params_ok(p)) return SLIC_EINVAL;
+    Grid g;
+    compute_grid(p, &g);
+    if (S) *S = g.S;
+    if (ns_c) *ns_c = g.ns_c;
+    if (ns_r) *ns_r = g.ns_r;
+    return SLIC_OK;
+}
+
+int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* hip_stream,
+              void* d_ws, size_t ws_bytes) {
+    if (!out || !params_ok(p) || !d_rgb || !d_ws || !aligned(d_ws)) return SLIC_EINVAL;
+    *out = nullptr;
+    if (ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc) return rc;
+    slic_ctx* c = new (std::nothrow) slic_ctx;
+    if (!c) return SLIC_ENOMEM;
+    c->p = *p;
+    compute_grid(p, &c->g);
+    workspace_layout(p->width, p->height, c->g, &c->ws, static_cast<char*>(d_ws));
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->state = 0;
+    c->ppt = 0;
+    c->t = 0;
+    if (hipGetDevice(&c->device) != hipSuccess || enqueue_init(c, d_rgb) != hipSuccess) {
+        delete c;
+        return SLIC_EHIP;
+    }
+    *out = c;
+    return SLIC_OK;
+}
+
+int slic_iterate(slic_ctx* c, int32_t n_iters) {
+    if (!c || n_iters < 0) return SLIC_EINVAL;
+    if (c->state != 0) return SLIC_ESTATE;
+    return enqueue_iterations(c, n_iters) == hipSuccess ? SLIC_OK : fail(c);
+}
+
+int slic_enforce_connectivity(slic_ctx* c, int32_t* d_n_segments) {
+    if (!c) return SLIC_EINVAL;
+    if (c->state != 0) return SLIC_ESTATE;
+    if (launch_connectivity(c->ws, c->p.width, c->p.height, c->g, c->p.min_segment, c->ws.labels,
+                            d_n_segments, c->stream) != hipSuccess)
+        return fail(c);
+    c->state = 1;
+    return SLIC_OK;
+}
+
+int slic_get_labels(const slic_ctx* c, int32_t* d_labels) {
+    if (!c || !d_labels) return SLIC_EINVAL;
+    if (c->state == 2) return SLIC_ESTATE;
+    const size_t bytes = static_cast<size_t>(c->p.width) * c->p.height * sizeof(int32_t);
+    if (hipMemcpyAsync(d_labels, c->ws.labels, bytes, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+        return fail(const_cast<slic_ctx*>(c));
+    return SLIC_OK;
+}
+
+int slic_get_centres(const slic_ctx* c, float* d_centres, int32_t* d_counts) {
+    if (!c || !d_centres) return SLIC_EINVAL;
+    if (c->state == 2) return SLIC_ESTATE;
+    if (launch_export_centres(c->ws, c->g, d_centres, d_counts, c->stream) != hipSuccess)
+        return fail(const_cast<slic_ctx*>(c));
+    return SLIC_OK;
+}
+
+int slic_get_lab(const slic_ctx* c, float* d_L, float* d_a, float* d_b) {
+    if (!c || !d_L || !d_a || !d_b) return SLIC_EINVAL;
+    if (c->state == 2) return SLIC_ESTATE;
+    const size_t bytes = static_cast<size_t>(c->p.width) * c->p.height * sizeof(float);
+    const float* src[3] = {c->ws.L, c->ws.A, c->ws.B};
+    float* dst[3] = {d_L, d_a, d_b};
+    for (int j = 0; j < 3; ++j)
+        if (hipMemcpyAsync(dst[j], src[j], bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return fail(const_cast<slic_ctx*>(c));
+    return SLIC_OK;
+}
+
+int slic_energy(const slic_ctx* c, double* d_out) {
+    if (!c || !d_out) return SLIC_EINVAL;
+    if (c->state != 0) return SLIC_ESTATE;
+    if (launch_energy(c->ws, c->p.width, c->p.height, c->g, d_out, c->stream) != hipSuccess)
+        return fail(const_cast<slic_ctx*>(c));
+    return SLIC_OK;
+}
+
+int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, int32_t enforce,
+                 int32_t* d_labels, float* d_centres, double* d_energy, int32_t* d_n_segments,
+                 void* hip_stream, void* d_ws, size_t ws_bytes) {
+    if (!params_ok(p) || !d_rgb || !d_labels || !d_ws || !aligned(d_ws) || n_iters < 0)
+        return SLIC_EINVAL;
+    if (ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc) return rc;
+    if ((rc = check_device_ptr(d_labels)) != 0) return rc;
+    slic_ctx c;
+    c.p = *p;
+    compute_grid(p, &c.g);
+    workspace_layout(p->width, p->height, c.g, &c.ws, static_cast<char*>(d_ws));
+    c.ws.labels = d_labels;  // associate straight into the caller's buffer
+    c.stream = static_cast<hipStream_t>(hip_stream);
+    c.state = 0;
+    c.ppt = 0;
+    c.t = 0;
+    c.device = 0;
+    if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
+    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
+    if (d_energy &&
+        launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
+                                       d_n_segments, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    return SLIC_OK;
+}
+
+void slic_destroy(slic_ctx* c) { delete c; }
+
+const char* slic_strerror(int code) {
+    switch (code) {
+        case SLIC_OK: return "ok";
+        case SLIC_EINVAL: return "invalid argument";
+        case SLIC_ENOMEM: return "out of host memory";
+        case SLIC_EHIP: return "HIP runtime error";
+        case SLIC_ESTATE: return "invalid context state";
+        default: return "unknown error";
+    }
+}
+
+int slic_timing_enable(int32_t on) {
+    if (on) {
+        for (const TimedLaunch& t : g_launches) {
+            g_event_pool.push_back(t.start);
+            g_event_pool.push_back(t.stop);
+        }
+        g_launches.clear();
+    }
+    g_timing = on != 0;
+    return SLIC_OK;
+}
+
+int slic_timing_read(const char* prefix, double* total_ms, int64_t* launches) {
+    double sum = 0.0;
+    int64_t cnt = 0;
+    const size_t plen = prefix ? std::strlen(prefix) : 0;
+    for (const TimedLaunch& t : g_launches) {
+        if (prefix && std::strncmp(t.name, prefix, plen) != 0) continue;
+        float ms = 0.0f;
+        if (hipEventSynchronize(t.stop) != hipSuccess ||
+            hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess)
+            return SLIC_EHIP;
+        sum += ms;
+        ++cnt;
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = cnt;
+    return SLIC_OK;
+}
+
+}  // extern "C"

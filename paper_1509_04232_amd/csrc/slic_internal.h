@@ -1,0 +1,92 @@
+// Internal declarations of libslic (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "slic.h"
+
+namespace slic {
+
+// Colour values enter the centre sums as exact integers rint(v * 2^18).
+// |v| < 108 for every sRGB colour, so |q| < 2^25 and a 64-lane sum of q
+// fits in int32.
+constexpr int kQShift = 18;
+
+// Centres are stored padded to 8 floats (L, a, b, x, y, -, -, -) so a
+// centre is two aligned 16-byte loads.
+constexpr int kCenStride = 8;
+
+// Per-cluster accumulators: sum qL, qa, qb, x, y and the pixel count.
+constexpr int kSumStride = 6;
+
+struct Grid {
+    int32_t S, ns_c, ns_r, K;
+    float w;  // m / S in FP32, the factor of d_xy in Eq. 1
+};
+
+struct Workspace {
+    float *L, *A, *B;    // planar CIELAB, N each
+    int32_t* labels;     // N, cluster index per pixel
+    float* cen;          // K x kCenStride
+    int32_t* counts;     // K, pixels per centre at the last update
+    long long* sums;     // 3 x K x kSumStride, a ring of accumulators
+    int32_t *ccl0, *ccl1, *ccl2, *ccl3;  // N each, connectivity scratch
+    int32_t* scan;       // block totals of the connectivity prefix sum
+    double* partial;     // per-block energy partial sums
+    int32_t n_scan_blocks, n_energy_blocks;
+};
+
+// Byte offsets of the workspace parts; returns the total size.
+size_t workspace_layout(int32_t width, int32_t height, const Grid& g, Workspace* ws, char* base);
+
+// Number of prefix-sum tiles the connectivity pass uses for n pixels.
+int scan_tiles_for(int n);
+
+// Launch wrappers (each returns the hipError_t of its launches).
+hipError_t launch_lab(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int32_t channels,
+                      float* L, float* A, float* B, hipStream_t s);
+hipError_t launch_seed(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int perturb,
+                       hipStream_t s);
+// Association launch number t (0: the first, with the seeds as centres;
+// t >= 1 also completes the centre update of the previous launch).
+// ppt: pixels per thread (1, 2 or 4), or 0 to choose from the image size.
+hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
+                         int ppt, hipStream_t s);
+int assign_pixels_per_thread(int32_t w, int32_t h);
+hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,
+                         hipStream_t s);
+hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                               int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
+                               hipStream_t s);
+hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out, int32_t* counts,
+                                 hipStream_t s);
+
+// Kernel timing: while enabled, a KernelTimer brackets a launch with HIP
+// events on the launch stream.
+bool timing_enabled();
+class KernelTimer {
+  public:
+    KernelTimer(const char* name, hipStream_t s);
+    ~KernelTimer();
+
+  private:
+    const char* name_;
+    hipStream_t s_;
+    void* start_;
+};
+
+}  // namespace slic
+
+struct slic_ctx {
+    slic_params p;
+    slic::Grid g;
+    slic::Workspace ws;
+    hipStream_t stream;
+    int device;
+    int ppt;        // association pixels per thread
+    int64_t t;      // association launches so far
+    int state;      // 0: k-means state valid, 1: connectivity done, 2: poisoned
+};

@@ -1,0 +1,118 @@
+"""The C-ABI library loads, exports every entry point ``include/slic.h``
+declares, and its pure-host logic (parameter validation, grid, workspace
+sizing, error strings) behaves as documented.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slic.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1509_04232_amd import _abi
+    return _abi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slic_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(abi):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(abi.lib, n), f"{n} declared in slic.h but not exported"
+    assert set(names) == set(abi.EXPORTED)
+
+
+def _p(abi, **kw):
+    d = dict(width=640, height=480, pitch=0, channels=3, S=16, K=0, m=10.0, flags=1, min_segment=0)
+    d.update(kw)
+    if d["pitch"] == 0:
+        d["pitch"] = d["width"] * d["channels"]
+    return abi.SlicParams(**d)
+
+
+@pytest.mark.parametrize("w,h,S,K", [(640, 480, 16, 0), (1920, 1080, 8, 0), (1920, 1080, 16, 0),
+                                     (640, 480, 0, 1200), (5, 3, 0, 1000), (7, 5, 100, 0),
+                                     (1, 1, 1, 0), (3631, 3859, 0, 2000)])
+def test_grid_matches_oracle_reading(abi, w, h, S, K):
+    assert abi.slic_grid(_p(abi, width=w, height=h, S=S, K=K)) == oracle.grid(w, h, S, K)
+
+
+@pytest.mark.parametrize("bad", [dict(width=0), dict(height=-1), dict(channels=2),
+                                 dict(pitch=10), dict(S=-1), dict(S=0, K=0), dict(m=-1.0),
+                                 dict(m=float("nan")), dict(m=float("inf")), dict(flags=2),
+                                 dict(min_segment=-1), dict(width=1 << 25, height=1),
+                                 dict(width=40000, height=40000)])
+def test_invalid_params_rejected(abi, bad):
+    p = _p(abi, **bad)
+    assert abi.lib.slic_workspace_bytes(ctypes.byref(p)) == 0
+    assert abi.lib.slic_grid(ctypes.byref(p), None, None, None) == abi.SLIC_EINVAL
+    ctx = ctypes.c_void_p()
+    assert abi.lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), 256, None, 256, 1 << 30) == \
+        abi.SLIC_EINVAL
+    assert ctx.value is None
+
+
+def test_workspace_size_grows_with_the_image(abi):
+    small = abi.slic_workspace_bytes(_p(abi, width=320, height=240))
+    big = abi.slic_workspace_bytes(_p(abi, width=1920, height=1080, S=8))
+    assert 0 < small < big
+    n = 1920 * 1080
+    assert big >= n * (3 * 4 + 4 + 4 * 4)  # Lab, labels, connectivity scratch
+    assert big % 256 == 0
+
+
+def test_init_rejects_small_or_misaligned_workspace(abi):
+    p = _p(abi)
+    need = abi.slic_workspace_bytes(p)
+    ctx = ctypes.c_void_p()
+    assert abi.lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), 256, None, 256, need - 1) == \
+        abi.SLIC_EINVAL
+    assert abi.lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), 256, None, 258, need) == \
+        abi.SLIC_EINVAL
+    assert abi.lib.slic_init(None, ctypes.byref(p), 256, None, 256, need) == abi.SLIC_EINVAL
+
+
+def test_null_context_calls(abi):
+    assert abi.lib.slic_iterate(None, 1) == abi.SLIC_EINVAL
+    assert abi.lib.slic_enforce_connectivity(None, None) == abi.SLIC_EINVAL
+    assert abi.lib.slic_get_labels(None, 256) == abi.SLIC_EINVAL
+    assert abi.lib.slic_energy(None, 256) == abi.SLIC_EINVAL
+    abi.lib.slic_destroy(None)
+
+
+def test_strerror(abi):
+    assert abi.slic_strerror(0) == "ok"
+    assert abi.slic_strerror(abi.SLIC_EINVAL) == "invalid argument"
+    assert abi.slic_strerror(abi.SLIC_EHIP) == "HIP runtime error"
+    assert abi.slic_strerror(99) == "unknown error"
+
+
+def test_timing_read_without_launches(abi):
+    abi.slic_timing_enable(True)
+    assert abi.slic_timing_read("assign") == (0.0, 0)
+    abi.slic_timing_enable(False)
+
+
+def test_no_device_is_an_error_not_a_fallback(abi):
+    """Without a GPU the library reports SLIC_EHIP (or rejects the fake
+    pointers) instead of computing anything on the host."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = _p(abi)
+    need = abi.slic_workspace_bytes(p)
+    ctx = ctypes.c_void_p()
+    rc = abi.lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), 4096, None, 8192, need)
+    assert rc in (abi.SLIC_EHIP, abi.SLIC_EINVAL)
+    assert ctx.value is None
