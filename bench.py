@@ -63,6 +63,11 @@ class Frame:
         self.nseg = torch.empty(1, dtype=torch.int32, device=device)
         self.stream = torch.cuda.current_stream().cuda_stream
         self.K = self.p.n_clusters
+        # the library's autotuner picks the association launch variant for
+        # this image size and step (recorded process-wide)
+        self.variant, self.tuned_ms_per_iter = slic.slic_autotune(
+            self.cp, self.rgb.data_ptr(), wl.iters, 5, self.stream, self.ws.data_ptr(),
+            self.ws.numel())
 
     def run(self, iters: int, enforce: bool) -> None:
         self.slic.slic_segment(self.cp, self.rgb.data_ptr(), iters, 1 if enforce else 0,
@@ -83,7 +88,7 @@ def time_frames(torch, frame: Frame, steps: int, warmup: int, iters: int, enforc
     return (time.perf_counter() - t0) / steps
 
 
-KERNELS = ("lab", "seed", "assign", "finalize", "ccl_", "energy")
+KERNELS = ("lab_seed", "assign", "ccl_", "energy")
 
 
 def kernel_times(slic, torch, frame: Frame, steps: int, iters: int, enforce: bool):
@@ -147,6 +152,9 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (PMC calibration)")
+    ap.add_argument("--workload-only", default=None, metavar="NAME",
+                    help="profiling mode: run warmup+steps frames of workload NAME (c1, c2, c3) "
+                         "and the optional copy, print one line per phase, no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the SLIC path has no multi-GPU mode "
@@ -164,6 +172,22 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.workload_only:
+        w = synth.WORKLOADS[args.workload_only]
+        f = Frame(slic, w, dev)
+        for _ in range(args.warmup + args.steps):
+            f.run(w.iters, w.connectivity)
+        torch.cuda.synchronize()
+        print(f"ran {args.warmup + args.steps} frames of {w.name}", flush=True)
+        if args.copy_bytes > 0:
+            src = torch.ones(args.copy_bytes, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            print(f"copied {args.copy_bytes} bytes 3 times", flush=True)
+        return 0
+
     wl = synth.WORKLOADS["c2"]
     frame = Frame(slic, wl, dev)
     sec = time_frames(torch, frame, args.steps, args.warmup, wl.iters, wl.connectivity)
@@ -175,7 +199,10 @@ def main() -> int:
     achieved = nbytes / (a_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic_from_profile(), "kernel": "assign_kernel",
+                "traffic": traffic_from_profile(),
+                "kernel": f"assign_kernel (variant {frame.variant}: "
+                          f"{'x'.join(map(str, slic.slic_assign_variant_info(frame.variant)[:2]))} "
+                          f"pixels per thread)",
                 "bytes_per_launch": nbytes, "avg_launch_us": round(a_ms * 1e3, 3)}
 
     extra = {"kernels_c2": {k: {"avg_us": round(v["avg_ms"] * 1e3, 3),
@@ -197,6 +224,7 @@ def main() -> int:
                 a = kt["assign"]["avg_ms"]
                 b = assign_bytes(w.n_pixels, f.K)
                 entry["assign_avg_us"] = round(a * 1e3, 3)
+                entry["assign_variant"] = f.variant
                 entry["assign_gbps"] = round(b / (a * 1e-3) / 1e9, 1)
                 entry["assign_hbm_frac"] = round(b / (a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             extra[name] = entry

@@ -126,6 +126,29 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
 void slic_destroy(slic_ctx* ctx);
 const char* slic_strerror(int code);
 
+/* Launch variants of the association kernel (Section 3's per-pixel step)
+ * and their autotuner.  Every variant computes bit-identical results; they
+ * differ in the pixels each thread owns (vec horizontally adjacent pixels in
+ * each of `rows` rows) and hence the workgroup's tile.  Variant ids run from
+ * 1 to slic_assign_variants().  The choice is kept per (width, height, S) in
+ * a process-wide table that contexts read when they are created.
+ *  - slic_assign_variant_info: the shape of a variant (outputs may be NULL).
+ *  - slic_set_assign_variant: record a variant (0: back to the built-in
+ *    choice); SLIC_EINVAL if the variant cannot run that shape.
+ *  - slic_get_assign_variant: the variant a new context would use.
+ *  - slic_autotune: times `reps` runs of slic_init + n_iters iterations for
+ *    every variant that supports p (after one warm-up run each), on the given
+ *    image, stream and workspace, records the fastest in the table and returns
+ *    it with its time per iteration in milliseconds.  Synchronises the host. */
+int32_t slic_assign_variants(void);
+int slic_assign_variant_info(int32_t variant, int32_t* vec, int32_t* rows, int32_t* tile_w,
+                             int32_t* tile_h);
+int slic_set_assign_variant(int32_t width, int32_t height, int32_t S, int32_t variant);
+int slic_get_assign_variant(int32_t width, int32_t height, int32_t S, int32_t* variant);
+int slic_autotune(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, int32_t reps,
+                  void* hip_stream, void* d_ws, size_t ws_bytes, int32_t* best_variant,
+                  float* best_ms_per_iter);
+
 /* Kernel timing for measurement.  slic_timing_enable(1) forgets earlier
  * records and starts recording: every kernel launch of the library is then
  * bracketed by HIP events on the stream it is launched on.

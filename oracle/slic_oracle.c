@@ -71,30 +71,33 @@ int orc_grid(int32_t w, int32_t h, int32_t S_in, int32_t K_in, int32_t* S_out,
  * R,G,B byte order, FP32 output.
  * ---------------------------------------------------------------------- */
 
-/* Cube root by Newton's method on y^3 = t, t > 0 and normal.  t = f*2^e with
- * f in [0.5,1); e is shifted to a multiple of three so that g = f*2^r lies in
- * [0.5,4) and cbrt(t) = cbrt(g)*2^q.  A quadratic seed on that interval has
- * relative error below 1.7%; each step y <- (2y^3 + g)/(3y^2) squares the
- * error, so four steps reach the double-precision fixed point (within two
- * ulps of the true root).  cbrt(1) is exactly 1. */
+/* Cube root of t > 0 (normal).  t = f*2^e with f in [0.5,1); e is shifted
+ * to a multiple of three so that g = f*2^r lies in [0.5,4) and
+ * cbrt(t) = cbrt(g)*2^q.  Newton's method on the inverse cube root,
+ * y <- y + y(1 - g y^3)/3, needs no division; a quadratic seed on [0.5,4)
+ * has relative error below 4.2%, each step squares the error, so four steps
+ * reach the double-precision fixed point.  Then cbrt(g) = g*y*y, within
+ * three ulps of the true root; cbrt(1) is exactly 1. */
 static double orc_cbrt(double t) {
     int e;
     double f = frexp(t, &e);
     int r = ((e % 3) + 3) % 3;
     double g = ldexp(f, r);
     int q = (e - r) / 3;
-    double lin = 0.6052 + 0.4255 * g;
+    double lin = 1.405 - 0.4258 * g;
     double g2 = g * g;
-    double y = lin - 0.04658 * g2;
+    double y = lin + 0.05965 * g2;
+    const double third = 1.0 / 3.0;
     for (int i = 0; i < 4; i++) {
         double y2 = y * y;
         double y3 = y2 * y;
-        double num = 2.0 * y3;
-        num = num + g;
-        double den = 3.0 * y2;
-        y = num / den;
+        double err = fma(-g, y3, 1.0);
+        double corr = y * err;
+        y = fma(corr, third, y);
     }
-    return ldexp(y, q);
+    double c = g * y;
+    c = c * y;
+    return ldexp(c, q);
 }
 
 double orc_cbrt_export(double t) { return orc_cbrt(t); }

@@ -12,10 +12,12 @@ import torch
 
 from . import _abi
 from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, SLIC_OK,
-                   SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_destroy,
-                   slic_enforce_connectivity, slic_energy, slic_get_centres, slic_get_lab,
-                   slic_get_labels, slic_grid, slic_init, slic_iterate, slic_segment,
-                   slic_strerror, slic_timing_enable, slic_timing_read, slic_workspace_bytes)
+                   SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_assign_variant_info,
+                   slic_assign_variants, slic_autotune, slic_destroy,
+                   slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
+                   slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
+                   slic_iterate, slic_segment, slic_set_assign_variant, slic_strerror,
+                   slic_timing_enable, slic_timing_read, slic_workspace_bytes)
 
 __all__ = [
     "Params", "Context", "segment", "workspace_for", "SlicError", "SlicParams", *EXPORTED,

@@ -53,6 +53,11 @@ _SIGS = {
     "slic_segment": ([_PP, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_destroy": ([_P], None),
     "slic_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "slic_assign_variants": ([], ctypes.c_int32),
+    "slic_assign_variant_info": ([_I, _P, _P, _P, _P], ctypes.c_int),
+    "slic_set_assign_variant": ([_I, _I, _I, _I], ctypes.c_int),
+    "slic_get_assign_variant": ([_I, _I, _I, _P], ctypes.c_int),
+    "slic_autotune": ([_PP, _P, _I, _I, _P, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
     "slic_timing_enable": ([_I], ctypes.c_int),
     "slic_timing_read": ([ctypes.c_char_p, _P, _P], ctypes.c_int),
 }
@@ -126,6 +131,38 @@ def slic_destroy(ctx: int) -> None:
 
 def slic_strerror(code: int) -> str:
     return lib.slic_strerror(code).decode()
+
+
+def slic_assign_variants() -> int:
+    return int(lib.slic_assign_variants())
+
+
+def slic_assign_variant_info(variant: int):
+    """(vec, rows, tile_w, tile_h) of an association launch variant."""
+    out = [ctypes.c_int32() for _ in range(4)]
+    _check(lib.slic_assign_variant_info(variant, *[ctypes.byref(o) for o in out]),
+           "slic_assign_variant_info")
+    return tuple(int(o.value) for o in out)
+
+
+def slic_set_assign_variant(width: int, height: int, S: int, variant: int) -> None:
+    _check(lib.slic_set_assign_variant(width, height, S, variant), "slic_set_assign_variant")
+
+
+def slic_get_assign_variant(width: int, height: int, S: int) -> int:
+    v = ctypes.c_int32()
+    _check(lib.slic_get_assign_variant(width, height, S, ctypes.byref(v)), "slic_get_assign_variant")
+    return int(v.value)
+
+
+def slic_autotune(p: SlicParams, d_rgb: int, n_iters: int, reps: int, stream: int, d_ws: int,
+                  ws_bytes: int):
+    """(best variant, milliseconds per iteration); records the choice."""
+    best = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(lib.slic_autotune(ctypes.byref(p), d_rgb, n_iters, reps, stream, d_ws, ws_bytes,
+                             ctypes.byref(best), ctypes.byref(ms)), "slic_autotune")
+    return int(best.value), float(ms.value)
 
 
 def slic_timing_enable(on: bool) -> None:

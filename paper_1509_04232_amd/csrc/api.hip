@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "slic_internal.h"
@@ -155,14 +158,11 @@ int check_buffers(const void* rgb, const void* ws) {
 // Section 4's listing up to the first association.
 hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb) {
     const slic_params& p = c->p;
-    hipError_t e = launch_lab(rgb, p.width, p.height, p.pitch, p.channels, c->ws.L, c->ws.A,
-                              c->ws.B, c->stream);
-    if (e != hipSuccess) return e;
-    e = launch_seed(c->ws, p.width, p.height, c->g, (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0,
-                    c->stream);
+    hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
+                                   (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
     if (e != hipSuccess) return e;
     c->t = 0;
-    e = launch_assign(c->ws, p.width, p.height, c->g, c->t, c->ppt, c->stream);
+    e = launch_assign(c->ws, p.width, p.height, c->g, c->t, c->variant, c->stream);
     if (e == hipSuccess) c->t = 1;
     return e;
 }
@@ -171,7 +171,7 @@ hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb) {
 // the previous launch's centre update.
 hipError_t enqueue_iterations(slic_ctx* c, int32_t n) {
     for (int32_t i = 0; i < n; ++i) {
-        hipError_t e = launch_assign(c->ws, c->p.width, c->p.height, c->g, c->t, c->ppt, c->stream);
+        hipError_t e = launch_assign(c->ws, c->p.width, c->p.height, c->g, c->t, c->variant, c->stream);
         if (e != hipSuccess) return e;
         ++c->t;
     }
@@ -181,6 +181,31 @@ hipError_t enqueue_iterations(slic_ctx* c, int32_t n) {
 int fail(slic_ctx* c) {
     if (c) c->state = 2;
     return SLIC_EHIP;
+}
+
+// Process-wide choice of association variant per (width, height, S),
+// filled by slic_set_assign_variant or slic_autotune.
+std::mutex g_variant_mu;
+std::map<std::tuple<int32_t, int32_t, int32_t>, int> g_variant;
+
+int resolve_variant(int32_t w, int32_t h, int32_t S) {
+    {
+        std::lock_guard<std::mutex> lock(g_variant_mu);
+        auto it = g_variant.find(std::make_tuple(w, h, S));
+        if (it != g_variant.end() && assign_variant_supported(it->second, w, h, S)) return it->second;
+    }
+    return assign_default_variant(w, h, S);
+}
+
+void bind(slic_ctx* c, const slic_params* p, void* d_ws, void* stream) {
+    c->p = *p;
+    compute_grid(p, &c->g);
+    workspace_layout(p->width, p->height, c->g, &c->ws, static_cast<char*>(d_ws));
+    c->stream = static_cast<hipStream_t>(stream);
+    c->state = 0;
+    c->variant = resolve_variant(p->width, p->height, c->g.S);
+    c->t = 0;
+    c->device = 0;
 }
 
 }  // namespace
@@ -216,13 +241,7 @@ int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* 
     if (rc) return rc;
     slic_ctx* c = new (std::nothrow) slic_ctx;
     if (!c) return SLIC_ENOMEM;
-    c->p = *p;
-    compute_grid(p, &c->g);
-    workspace_layout(p->width, p->height, c->g, &c->ws, static_cast<char*>(d_ws));
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->state = 0;
-    c->ppt = 0;
-    c->t = 0;
+    bind(c, p, d_ws, hip_stream);
     if (hipGetDevice(&c->device) != hipSuccess || enqueue_init(c, d_rgb) != hipSuccess) {
         delete c;
         return SLIC_EHIP;
@@ -295,15 +314,8 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
     if (rc) return rc;
     if ((rc = check_device_ptr(d_labels)) != 0) return rc;
     slic_ctx c;
-    c.p = *p;
-    compute_grid(p, &c.g);
-    workspace_layout(p->width, p->height, c.g, &c.ws, static_cast<char*>(d_ws));
+    bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;  // associate straight into the caller's buffer
-    c.stream = static_cast<hipStream_t>(hip_stream);
-    c.state = 0;
-    c.ppt = 0;
-    c.t = 0;
-    c.device = 0;
     if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
     if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
@@ -318,6 +330,91 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
 }
 
 void slic_destroy(slic_ctx* c) { delete c; }
+
+int32_t slic_assign_variants(void) { return assign_variant_count(); }
+
+int slic_assign_variant_info(int32_t variant, int32_t* vec, int32_t* rows, int32_t* tile_w,
+                             int32_t* tile_h) {
+    int v = 0, r = 0, tw = 0, th = 0;
+    if (!assign_variant_shape(variant, &v, &r, &tw, &th)) return SLIC_EINVAL;
+    if (vec) *vec = v;
+    if (rows) *rows = r;
+    if (tile_w) *tile_w = tw;
+    if (tile_h) *tile_h = th;
+    return SLIC_OK;
+}
+
+int slic_set_assign_variant(int32_t width, int32_t height, int32_t S, int32_t variant) {
+    if (width < 1 || height < 1 || S < 1) return SLIC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_variant_mu);
+    const auto key = std::make_tuple(width, height, S);
+    if (variant == 0) {
+        g_variant.erase(key);
+        return SLIC_OK;
+    }
+    if (!assign_variant_supported(variant, width, height, S)) return SLIC_EINVAL;
+    g_variant[key] = variant;
+    return SLIC_OK;
+}
+
+int slic_get_assign_variant(int32_t width, int32_t height, int32_t S, int32_t* variant) {
+    if (width < 1 || height < 1 || S < 1 || !variant) return SLIC_EINVAL;
+    *variant = resolve_variant(width, height, S);
+    return SLIC_OK;
+}
+
+int slic_autotune(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, int32_t reps,
+                  void* hip_stream, void* d_ws, size_t ws_bytes, int32_t* best_variant,
+                  float* best_ms_per_iter) {
+    if (!params_ok(p) || !d_rgb || !d_ws || !aligned(d_ws) || n_iters < 1 || reps < 1)
+        return SLIC_EINVAL;
+    if (ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SLIC_EHIP;
+    slic_ctx c;
+    bind(&c, p, d_ws, hip_stream);
+    int best = 0;
+    float best_ms = 0.0f;
+    rc = SLIC_OK;
+    for (int v = 1; v <= assign_variant_count() && rc == SLIC_OK; ++v) {
+        if (!assign_variant_supported(v, p->width, p->height, c.g.S)) continue;
+        c.variant = v;
+        float total = 0.0f;
+        for (int r = 0; r <= reps; ++r) {  // the first round warms up
+            c.state = 0;
+            if (enqueue_init(&c, d_rgb) != hipSuccess ||
+                hipEventRecord(e0, c.stream) != hipSuccess ||
+                enqueue_iterations(&c, n_iters) != hipSuccess ||
+                hipEventRecord(e1, c.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = SLIC_EHIP;
+                break;
+            }
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = SLIC_EHIP;
+                break;
+            }
+            if (r > 0) total += ms;
+        }
+        const float per_iter = total / static_cast<float>(reps * n_iters);
+        if (rc == SLIC_OK && (best == 0 || per_iter < best_ms)) {
+            best = v;
+            best_ms = per_iter;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SLIC_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_variant_mu);
+        g_variant[std::make_tuple(p->width, p->height, c.g.S)] = best;
+    }
+    if (best_variant) *best_variant = best;
+    if (best_ms_per_iter) *best_ms_per_iter = best_ms;
+    return SLIC_OK;
+}
 
 const char* slic_strerror(int code) {
     switch (code) {

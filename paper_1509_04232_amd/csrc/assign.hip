@@ -10,12 +10,16 @@
 // so ties go to the lowest index.
 //
 // Certified fast path.  The kernel first evaluates every candidate with fused
-// multiply-adds and the hardware square root, keeping the smallest and the
-// second smallest value.  Each fast value is within 11 u of the exact real
-// distance and each reference value within 4 u (u = 2^-24; relative, all
-// terms are non-negative), so if the best fast value is below the second
-// smallest by more than 2^-18 of the latter, the reference argmin is the same
-// candidate and no reference value can tie with it.  Otherwise (near ties)
+// multiply-adds and the hardware square root.  It tracks the smallest and
+// second smallest value as integer keys: the distance's bit pattern (a
+// non-negative float orders like its bits) with the low four bits replaced
+// by the candidate number, so one integer min and one median-of-three keep
+// both, and the smallest key names the candidate (lowest index first).  Each
+// fast value is within 11 u of the exact real distance and each reference
+// value within 4 u (u = 2^-24; relative, all terms are non-negative); the
+// keys drop at most 2^-19 relative.  So if the best key's distance is below
+// the second's by more than 2^-17 of the latter, the reference argmin is the
+// same candidate and no reference value ties with it.  Otherwise (near ties)
 // the pixel recomputes every candidate with the reference sequence.
 //
 // Update, accumulation half: the pixel's colour enters its cluster's sums as
@@ -38,9 +42,8 @@
 namespace slic {
 namespace {
 
-constexpr int kTileX = 32;       // pixels per workgroup row
-constexpr int kThreads = 256;    // 32 x 8 threads; each thread owns PPT rows
-constexpr float kCertify = 0x1p-18f;
+constexpr int kThreads = 256;
+constexpr float kCertify = 0x1p-17f;
 
 // Reference Eq. 1 distance: the exact operation sequence of the definition.
 __device__ __forceinline__ float eq1_reference(float cl, float ca, float cb, float cx, float cy,
@@ -59,14 +62,35 @@ __device__ __forceinline__ float eq1_reference(float cl, float ca, float cb, flo
     return dlab + sp;
 }
 
-// Fast Eq. 1 distance (fused multiply-adds, hardware square root).
-__device__ __forceinline__ float eq1_fast(float cl, float ca, float cb, float cx, float cy, float l,
-                                          float a, float b, float xf, float yf, float wgt) {
+// Fast Eq. 1 distance (fused multiply-adds, hardware square root); dy2 is
+// the squared vertical offset, shared by the pixels of a row.
+__device__ __forceinline__ float eq1_fast(float cl, float ca, float cb, float cx, float dy2,
+                                          float l, float a, float b, float xf, float wgt) {
     const float dl = cl - l, da = ca - a, db = cb - b;
     const float s = __builtin_fmaf(db, db, __builtin_fmaf(da, da, dl * dl));
-    const float dx = cx - xf, dy = cy - yf;
-    const float t = __builtin_fmaf(dy, dy, dx * dx);
+    const float dx = cx - xf;
+    const float t = __builtin_fmaf(dx, dx, dy2);
     return __builtin_fmaf(wgt, __builtin_amdgcn_sqrtf(t), __builtin_amdgcn_sqrtf(s));
+}
+
+// Reference argmin over the nine candidates of one pixel (near ties only):
+// kept out of line so the unrolled fast path stays small.
+__device__ __noinline__ int reference_slot(const float4* cen4, const float* ceny, int base,
+                                           int ncx, float l, float a, float b, float xf,
+                                           float yf, float wgt) {
+    float bref = 0.0f;
+    int sref = -1;
+#pragma unroll 1
+    for (int c = 0; c < 9; ++c) {
+        const int li = base + (c / 3) * ncx + (c % 3);
+        const float4 q = cen4[li];
+        const float d = eq1_reference(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, wgt);
+        if (sref < 0 || d < bref) {
+            bref = d;
+            sref = c;
+        }
+    }
+    return sref;
 }
 
 struct AssignArgs {
@@ -88,18 +112,68 @@ struct AssignArgs {
 //   float4 cen4[n] (L, a, b, x), float ceny[n], int kidx[n] (-1: none),
 //   u64 bins[4][n] (sum qL, sum qa, sum qb, packed x'|y'<<20|count<<40).
 __host__ __device__ inline size_t assign_lds_bytes(int ncells) {
-    return static_cast<size_t>(ncells) * (16 + 4 + 4 + 32);
+    return static_cast<size_t>(ncells) * (16 + 4 + 4 + 32) + 16;
 }
 
-template <int PPT>
+// Launch shape of a variant: each thread owns VEC horizontally adjacent
+// pixels in each of ROWS consecutive rows.  VEC = 4 uses 16-byte loads and
+// evaluates each staged centre once for the four pixels, so it needs the
+// four pixels in one cell (S % 4 == 0) and aligned rows (width % 4 == 0).
+template <int VEC, int ROWS>
+struct Shape {
+    static constexpr int kTX = VEC == 1 ? 32 : 16;  // threads per row
+    static constexpr int kTY = kThreads / kTX;
+    static constexpr int kTileW = kTX * VEC;
+    static constexpr int kTileH = kTY * ROWS;
+    static constexpr int kPx = VEC * ROWS;
+};
+
+__device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, int cell, int rl,
+                                        int ra, int rb, unsigned long long rxyc) {
+    atomicAdd(bins + cell, static_cast<unsigned long long>(static_cast<long long>(rl)));
+    atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(static_cast<long long>(ra)));
+    atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(static_cast<long long>(rb)));
+    atomicAdd(bins + 3 * ncells + cell, rxyc);
+}
+
+template <int VEC, int ROWS>
 __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
+    using Sh = Shape<VEC, ROWS>;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int kTileY = 8 * PPT;
-    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    const int x0 = blockIdx.x * Sh::kTileW, y0 = blockIdx.y * Sh::kTileH;
+    const int tx = threadIdx.x % Sh::kTX, ty = threadIdx.x / Sh::kTX;
+    const int x = x0 + tx * VEC;
+    const bool col_ok = x < g.w;
+
+    // ---- prefetch this thread's pixels (they do not depend on the centres)
+    float pl[ROWS][VEC], pa[ROWS][VEC], pb[ROWS][VEC];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + ty * ROWS + r;
+        if (col_ok && y < g.h) {
+            const size_t pi = static_cast<size_t>(y) * g.w + x;
+            if constexpr (VEC == 4) {
+                const float4 l4 = *reinterpret_cast<const float4*>(g.L + pi);
+                const float4 a4 = *reinterpret_cast<const float4*>(g.A + pi);
+                const float4 b4 = *reinterpret_cast<const float4*>(g.B + pi);
+                pl[r][0] = l4.x; pl[r][1] = l4.y; pl[r][2] = l4.z; pl[r][3] = l4.w;
+                pa[r][0] = a4.x; pa[r][1] = a4.y; pa[r][2] = a4.z; pa[r][3] = a4.w;
+                pb[r][0] = b4.x; pb[r][1] = b4.y; pb[r][2] = b4.z; pb[r][3] = b4.w;
+            } else {
+                pl[r][0] = g.L[pi];
+                pa[r][0] = g.A[pi];
+                pb[r][0] = g.B[pi];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) pl[r][v] = pa[r][v] = pb[r][v] = 0.0f;
+        }
+    }
+
     const int S = g.S;
     const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
-    const int gx_hi = (min(x0 + kTileX, g.w) - 1) / S + 1;
-    const int gy_hi = (min(y0 + kTileY, g.h) - 1) / S + 1;
+    const int gx_hi = (min(x0 + Sh::kTileW, g.w) - 1) / S + 1;
+    const int gy_hi = (min(y0 + Sh::kTileH, g.h) - 1) / S + 1;
     const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
     float4* cen4 = reinterpret_cast<float4*>(smem);
     float* ceny = reinterpret_cast<float*>(cen4 + ncells);
@@ -121,8 +195,8 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
         }
         const int k = cy * g.ns_c + cx;
         kidx[i] = k;
-        const bool owner = (cx * S) / kTileX == static_cast<int>(blockIdx.x) &&
-                           (cy * S) / kTileY == static_cast<int>(blockIdx.y);
+        const bool owner = (cx * S) / Sh::kTileW == static_cast<int>(blockIdx.x) &&
+                           (cy * S) / Sh::kTileH == static_cast<int>(blockIdx.y);
         float* c = g.cen + static_cast<size_t>(k) * kCenStride;
         float4 v;
         float vy;
@@ -161,85 +235,89 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
     }
     __syncthreads();
 
-    // ---- associate PPT vertically adjacent pixels per thread
-    const int tx = threadIdx.x % kTileX, ty = threadIdx.x / kTileX;
-    const int x = x0 + tx;
-    const float xf = static_cast<float>(x);
-    const int gx_rel = (x < g.w ? x / S : 0) - gx_lo - 1;  // window column of the left candidate
+    // ---- associate: fast distances for every candidate, shared by the VEC
+    // pixels of a row (they lie in one cell)
+    // window column of the left candidates (columns past the image edge use the
+    // tile's first cell, so every staged-window index stays in range)
+    const int gx_rel = (col_ok ? x / S : x0 / S) - gx_lo - 1;
+    int cellv[ROWS][VEC];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + ty * ROWS + r;
+        const float yf = static_cast<float>(y);
+        const int base = (min(y, g.h - 1) / S - gy_lo - 1) * ncx + gx_rel;
+        unsigned best[VEC], second[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) best[v] = second[v] = 0xFFFFFFFFu;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const int li = base + (c / 3) * ncx + (c % 3);
+            const float4 q = cen4[li];
+            const float dy = ceny[li] - yf;
+            const float dy2 = dy * dy;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                const float d = eq1_fast(q.x, q.y, q.z, q.w, dy2, pl[r][v], pa[r][v], pb[r][v],
+                                         static_cast<float>(x + v), g.wgt);
+                const unsigned key = (__float_as_uint(d) & ~15u) | static_cast<unsigned>(c);
+                // median of (best, second, key) given best <= second
+                second[v] = max(best[v], min(second[v], key));
+                best[v] = min(best[v], key);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            int slot = static_cast<int>(best[v] & 15u);
+            const float bf = __uint_as_float(best[v] & ~15u);
+            const float sf = __uint_as_float(second[v] & ~15u);
+            if (!(bf < __builtin_fmaf(sf, -kCertify, sf)))
+                slot = reference_slot(cen4, ceny, base, ncx, pl[r][v], pa[r][v], pb[r][v],
+                                      static_cast<float>(x + v), yf, g.wgt);
+            cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
+        }
+    }
+
+    // ---- labels, then runs of equal cells into the LDS bins
     const float scale = static_cast<float>(1 << kQShift);
     int run_cell = -1;
     int rl = 0, ra = 0, rb = 0;
     unsigned long long rxyc = 0;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int y = y0 + ty * PPT + j;
-        const bool valid = x < g.w && y < g.h;
-        if (!valid) continue;
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + ty * ROWS + r;
+        if (!col_ok || y >= g.h) continue;
         const size_t pi = static_cast<size_t>(y) * g.w + x;
-        const float l = g.L[pi], a = g.A[pi], b = g.B[pi];
-        const float yf = static_cast<float>(y);
-        const int base = (y / S - gy_lo - 1) * ncx + gx_rel;
-        float best = __builtin_huge_valf(), second = __builtin_huge_valf();
-        int slot = 0;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            const int li = base + (c / 3) * ncx + (c % 3);
-            const float4 q = cen4[li];
-            const float d = eq1_fast(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, g.wgt);
-            second = fminf(second, fmaxf(best, d));
-            slot = d < best ? c : slot;
-            best = fminf(best, d);
-        }
-        if (!(best < __builtin_fmaf(second, -kCertify, second))) {
-            // near tie: reference values, lowest index wins ties
-            float bref = __builtin_huge_valf();
-            slot = -1;
-            for (int c = 0; c < 9; ++c) {
-                const int li = base + (c / 3) * ncx + (c % 3);
-                const float4 q = cen4[li];
-                const float d = eq1_reference(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, g.wgt);
-                if (slot < 0 || d < bref) {
-                    bref = d;
-                    slot = c;
-                }
-            }
-        }
-        const int cell = base + (slot / 3) * ncx + (slot % 3);
-        g.labels[pi] = kidx[cell];
-        const int ql = static_cast<int>(rintf(l * scale));
-        const int qa = static_cast<int>(rintf(a * scale));
-        const int qb = static_cast<int>(rintf(b * scale));
-        const unsigned long long xyc = static_cast<unsigned long long>(x - x0) |
-                                       (static_cast<unsigned long long>(y - y0) << 20) |
-                                       (1ull << 40);
-        if (cell != run_cell) {
-            if (run_cell >= 0) {
-                atomicAdd(bins + run_cell, static_cast<unsigned long long>(static_cast<long long>(rl)));
-                atomicAdd(bins + ncells + run_cell,
-                          static_cast<unsigned long long>(static_cast<long long>(ra)));
-                atomicAdd(bins + 2 * ncells + run_cell,
-                          static_cast<unsigned long long>(static_cast<long long>(rb)));
-                atomicAdd(bins + 3 * ncells + run_cell, rxyc);
-            }
-            run_cell = cell;
-            rl = ql;
-            ra = qa;
-            rb = qb;
-            rxyc = xyc;
+        if constexpr (VEC == 4) {
+            *reinterpret_cast<int4*>(g.labels + pi) =
+                make_int4(kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]], kidx[cellv[r][3]]);
         } else {
-            rl += ql;
-            ra += qa;
-            rb += qb;
-            rxyc += xyc;
+            g.labels[pi] = kidx[cellv[r][0]];
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int cell = cellv[r][v];
+            const int ql = static_cast<int>(rintf(pl[r][v] * scale));
+            const int qa = static_cast<int>(rintf(pa[r][v] * scale));
+            const int qb = static_cast<int>(rintf(pb[r][v] * scale));
+            const unsigned long long xyc = static_cast<unsigned long long>(x + v - x0) |
+                                           (static_cast<unsigned long long>(y - y0) << 20) |
+                                           (1ull << 40);
+            if (cell != run_cell) {
+                if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
+                run_cell = cell;
+                rl = ql;
+                ra = qa;
+                rb = qb;
+                rxyc = xyc;
+            } else {
+                rl += ql;
+                ra += qa;
+                rb += qb;
+                rxyc += xyc;
+            }
         }
     }
-    if (run_cell >= 0) {
-        atomicAdd(bins + run_cell, static_cast<unsigned long long>(static_cast<long long>(rl)));
-        atomicAdd(bins + ncells + run_cell, static_cast<unsigned long long>(static_cast<long long>(ra)));
-        atomicAdd(bins + 2 * ncells + run_cell,
-                  static_cast<unsigned long long>(static_cast<long long>(rb)));
-        atomicAdd(bins + 3 * ncells + run_cell, rxyc);
-    }
+    if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
     __syncthreads();
 
     // ---- add the workgroup's bins to the global sums
@@ -310,30 +388,72 @@ __global__ __launch_bounds__(256) void export_centres_kernel(int K, const float*
     if (out_counts) out_counts[k] = counts[k];
 }
 
-template <int PPT>
-hipError_t launch_assign_ppt(const AssignArgs& a, hipStream_t s) {
-    constexpr int kTileY = 8 * PPT;
-    dim3 grid((a.w + kTileX - 1) / kTileX, (a.h + kTileY - 1) / kTileY);
-    // window of cells over any tile: at most (tile/S + 3) per side
-    const int ncx = (kTileX - 1) / a.S + 3 + 1, ncy = (kTileY - 1) / a.S + 3 + 1;
-    const size_t lds = assign_lds_bytes(ncx * ncy) + 16;
+template <int VEC, int ROWS>
+size_t variant_lds(int S) {
+    using Sh = Shape<VEC, ROWS>;
+    // window of cells over any tile: at most (tile - 1)/S + 4 per side
+    return assign_lds_bytes(((Sh::kTileW - 1) / S + 4) * ((Sh::kTileH - 1) / S + 4));
+}
+
+template <int VEC, int ROWS>
+hipError_t launch_variant(const AssignArgs& a, hipStream_t s) {
+    using Sh = Shape<VEC, ROWS>;
+    dim3 grid((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
     KernelTimer t("assign", s);
-    assign_kernel<PPT><<<grid, kThreads, lds, s>>>(a);
+    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(a.S), s>>>(a);
     return hipGetLastError();
 }
 
+struct VariantDesc {
+    int vec, rows;
+    size_t (*lds)(int);
+    hipError_t (*launch)(const AssignArgs&, hipStream_t);
+};
+
+const VariantDesc kVariants[] = {
+    {1, 1, variant_lds<1, 1>, launch_variant<1, 1>},
+    {1, 2, variant_lds<1, 2>, launch_variant<1, 2>},
+    {1, 4, variant_lds<1, 4>, launch_variant<1, 4>},
+    {4, 1, variant_lds<4, 1>, launch_variant<4, 1>},
+    {4, 2, variant_lds<4, 2>, launch_variant<4, 2>},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
 }  // namespace
 
-int assign_pixels_per_thread(int32_t w, int32_t h) {
-    // enough workgroups to fill 256 compute units several times over
+int assign_variant_count() { return kNumVariants; }
+
+bool assign_variant_shape(int variant, int* vec, int* rows, int* tile_w, int* tile_h) {
+    if (variant < 1 || variant > kNumVariants) return false;
+    const VariantDesc& d = kVariants[variant - 1];
+    const int tx = d.vec == 1 ? 32 : 16;
+    if (vec) *vec = d.vec;
+    if (rows) *rows = d.rows;
+    if (tile_w) *tile_w = tx * d.vec;
+    if (tile_h) *tile_h = (kThreads / tx) * d.rows;
+    return true;
+}
+
+bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S) {
+    (void)h;
+    if (variant < 1 || variant > kNumVariants) return false;
+    const VariantDesc& d = kVariants[variant - 1];
+    if (d.vec == 4 && (S % 4 != 0 || w % 4 != 0)) return false;
+    return d.lds(S) <= (64u << 10);
+}
+
+int assign_default_variant(int32_t w, int32_t h, int32_t S) {
     const long long n = static_cast<long long>(w) * h;
-    if (n >= (4ll << 20)) return 4;
-    if (n >= (1ll << 20)) return 2;
-    return 1;
+    // small frames are latency bound: the most workgroups; large frames
+    // amortise the staged centres over more pixels per thread
+    int v = 1;
+    if (n >= (1ll << 20)) v = assign_variant_supported(4, w, h, S) ? 4 : 2;
+    while (v > 1 && !assign_variant_supported(v, w, h, S)) --v;
+    return v;
 }
 
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int ppt, hipStream_t s) {
+                         int variant, hipStream_t s) {
     AssignArgs a;
     a.L = ws.L;
     a.A = ws.A;
@@ -351,17 +471,8 @@ hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     a.sums_acc = ws.sums + stride * static_cast<size_t>(t % 3);
     a.sums_prev = t > 0 ? ws.sums + stride * static_cast<size_t>((t + 2) % 3) : nullptr;
     a.sums_next = ws.sums + stride * static_cast<size_t>((t + 1) % 3);
-    if (ppt <= 0) ppt = assign_pixels_per_thread(w, h);
-    // keep the staged window within 64 KiB of LDS
-    while (ppt > 1 && assign_lds_bytes(((kTileX - 1) / g.S + 4) * ((8 * ppt - 1) / g.S + 4)) + 16 >
-                          (64u << 10))
-        ppt /= 2;
-    switch (ppt) {
-        case 1: return launch_assign_ppt<1>(a, s);
-        case 2: return launch_assign_ppt<2>(a, s);
-        case 4: return launch_assign_ppt<4>(a, s);
-        default: return hipErrorInvalidValue;
-    }
+    if (!assign_variant_supported(variant, w, h, g.S)) variant = assign_default_variant(w, h, g.S);
+    return kVariants[variant - 1].launch(a, s);
 }
 
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,

@@ -12,17 +12,15 @@
 //
 // GPU structure: concurrent union-find whose links always point from a
 // larger to a smaller index (so a tree's root is its minimum), first inside
-// 32 x 32 tiles in LDS, then across tile borders in global memory; path
-// following for the joins; an exclusive prefix sum over the surviving roots
-// for the numbering.  All integer, so the result is exact.
+// 32 x 32 tiles in LDS, then across tile borders in global memory; the joins
+// of step 3 are links in the same union-find; ballot counts and a
+// one-workgroup prefix sum over the surviving roots for the numbering.  All integer, so the result is exact.
 #include "slic_internal.h"
 
 namespace slic {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ __forceinline__ int load_relaxed(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -100,7 +98,10 @@ __device__ void lds_unite(int* P, int a, int b) {
 
 // Tile-local components.  Local indices follow raster order inside the
 // tile, so a local root (the smallest local index) is also the smallest
-// global index of the component's part in the tile.  Writes P[i] = global
+// global index of the component's part in the tile.  A wavefront holds two
+// 32-pixel tile rows; each pixel finds the head of its horizontal run of
+// equal labels from a ballot of run starts, and union-find then links run
+// heads only, once per vertical overlap of two runs.  Writes P[i] = global
 // index of i's local root, lroot[i] = its local index, and clears size[i].
 __global__ __launch_bounds__(kBlock) void ccl_local_kernel(const int32_t* __restrict__ labels,
                                                            int w, int h, int* __restrict__ P,
@@ -109,25 +110,37 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(const int32_t* __rest
     __shared__ int lab[kTilePx];
     __shared__ int par[kTilePx];
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int col = threadIdx.x % kTile;
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + li % kTile, y = y0 + li / kTile;
+        const int x = x0 + col, y = y0 + li / kTile;
         lab[li] = (x < w && y < h) ? labels[static_cast<size_t>(y) * w + x] : -1;
-        par[li] = li;
+    }
+    __syncthreads();
+    // every pixel links to the head (first pixel) of its run
+    const int half = (threadIdx.x & 63) >= 32 ? 32 : 0;  // which row of the wavefront
+    const unsigned upto = col == 31 ? 0xFFFFFFFFu : (2u << col) - 1u;
+    for (int j = 0; j < kPxPerThread; ++j) {
+        const int li = threadIdx.x + j * kBlock;
+        const bool start = col == 0 || lab[li] != lab[li - 1];
+        const unsigned row_starts = static_cast<unsigned>(__ballot(start) >> half);
+        par[li] = li - col + (31 - __clz(row_starts & upto));
     }
     __syncthreads();
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + li % kTile, y = y0 + li / kTile;
-        if (x >= w || y >= h) continue;
+        const int x = x0 + col, y = y0 + li / kTile;
+        if (x >= w || y >= h || li < kTile) continue;
         const int v = lab[li];
-        if (li % kTile > 0 && lab[li - 1] == v) lds_unite(par, li, li - 1);
-        if (li >= kTile && lab[li - kTile] == v) lds_unite(par, li, li - kTile);
+        if (lab[li - kTile] != v) continue;
+        // one union per vertical overlap of two runs: at its first column
+        if (col > 0 && lab[li - 1] == v && lab[li - 1 - kTile] == v) continue;
+        lds_unite(par, li, li - kTile);
     }
     __syncthreads();
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + li % kTile, y = y0 + li / kTile;
+        const int x = x0 + col, y = y0 + li / kTile;
         if (x >= w || y >= h) continue;
         const int r = lds_find(par, li);
         const size_t gi = static_cast<size_t>(y) * w + x;
@@ -184,122 +197,110 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int w, int h, int* 
     }
 }
 
-// For each root: its join target (itself unless small).
-__global__ __launch_bounds__(kBlock) void ccl_join_kernel(int n, int w, long long S2,
-                                                          int min_segment,
-                                                          const int* __restrict__ comp,
-                                                          const int* __restrict__ size,
-                                                          int* __restrict__ join) {
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    if (comp[r] != r) return;
-    const int sz = size[r];
-    const bool small = min_segment > 0 ? sz < min_segment : 4ll * sz < S2;
-    int j = r;
-    if (r != 0 && small) j = comp[(r % w) > 0 ? r - 1 : r - w];
-    join[r] = j;
+// Find with path halving: every visited node is re-linked to its
+// grandparent (still an ancestor, so concurrent finds stay correct).
+__device__ __forceinline__ int find_halving(int* P, int x) {
+    int p = load_relaxed(P + x);
+    while (p != x) {
+        const int gp = load_relaxed(P + p);
+        if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+        p = load_relaxed(P + x);
+    }
+    return x;
 }
 
-// For each root: the root of its join tree; flag[r] = 1 for surviving roots.
-__global__ __launch_bounds__(kBlock) void ccl_resolve_kernel(int n, const int* __restrict__ comp,
-                                                             const int* __restrict__ join,
-                                                             int* __restrict__ fin,
-                                                             int* __restrict__ flag) {
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    if (comp[r] != r) {
-        flag[r] = 0;
-        return;
+// Joins.  A small component (other than the one holding pixel 0) joins the
+// component of the pixel left of its root r, or above r at a row start;
+// both have smaller roots, so the joins form a forest whose tree roots are
+// the smallest indices of their trees and are exactly the components that
+// are not small (or hold pixel 0).  Each small root links itself under the
+// current root of its target (only its own thread links comp[r]; path
+// halving later shortens links, always to ancestors with smaller indices);
+// the tree roots are then found by path-halving finds in the relabel pass.  The workgroup numbers its
+// surviving roots (ballot prefix counts) and stores their count.
+constexpr int kMergeBlock = 1024;
+
+__global__ __launch_bounds__(kMergeBlock) void ccl_merge_kernel(
+    int n, int w, long long S2, int min_segment, int* comp, const int* __restrict__ size,
+    int* __restrict__ rank, int* __restrict__ block_count) {
+    __shared__ int wave_total[kMergeBlock / 64];
+    const int r = blockIdx.x * kMergeBlock + threadIdx.x;
+    bool survives = false;
+    if (r < n && load_relaxed(comp + r) == r) {
+        const int sz = size[r];
+        const bool small = min_segment > 0 ? sz < min_segment : 4ll * sz < S2;
+        if (r == 0 || !small) {
+            survives = true;
+        } else {
+            const int t = find_halving(comp, (r % w) > 0 ? r - 1 : r - w);
+            __hip_atomic_store(comp + r, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
-    int f = r;
-    int j = join[f];
-    while (j != f) {
-        f = j;
-        j = join[f];
+    const unsigned long long ballot = __ballot(survives);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_total[wave] = __popcll(ballot);
+    __syncthreads();
+    int offset = 0;
+    for (int j = 0; j < wave; ++j) offset += wave_total[j];
+    if (survives) rank[r] = offset + __popcll(ballot & ((1ull << lane) - 1ull));
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int j = 0; j < kMergeBlock / 64; ++j) total += wave_total[j];
+        block_count[blockIdx.x] = total;
     }
-    fin[r] = f;
-    flag[r] = f == r ? 1 : 0;
 }
 
-// Exclusive prefix sum, pass 1: per tile of kScanTile elements, in place,
-// and the tile's total.
-__global__ __launch_bounds__(kBlock) void scan_tiles_kernel(int n, int* __restrict__ v,
-                                                            int* __restrict__ tile_total) {
-    __shared__ int s[kBlock];
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int item[kScanItems];
-    int run = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        item[j] = base + j < n ? v[base + j] : 0;
-        const int t = item[j];
-        item[j] = run;
-        run += t;
-    }
-    s[threadIdx.x] = run;
+// One workgroup: exclusive scan of the per-block counts in place; the total
+// is the number of segments.
+__global__ __launch_bounds__(kBlock) void ccl_scan_kernel(int nblocks, int* __restrict__ count,
+                                                          int* __restrict__ n_segments) {
+    __shared__ int part[kBlock];
+    const int per = (nblocks + kBlock - 1) / kBlock;
+    const int lo = threadIdx.x * per, hi = min(lo + per, nblocks);
+    int sum = 0;
+    for (int j = lo; j < hi; ++j) sum += count[j];
+    part[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {  // Hillis-Steele inclusive scan
-        const int add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    const int excl = threadIdx.x > 0 ? s[threadIdx.x - 1] : 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j)
-        if (base + j < n) v[base + j] = item[j] + excl;
-    if (threadIdx.x == kBlock - 1) tile_total[blockIdx.x] = s[kBlock - 1];
-}
-
-// Pass 2 (one workgroup): exclusive scan of the tile totals; the grand total
-// goes to *count (if given).
-__global__ __launch_bounds__(kBlock) void scan_totals_kernel(int ntiles, int* __restrict__ t,
-                                                             int* __restrict__ count) {
-    __shared__ int s[kBlock];
-    int carry = 0;
-    for (int base = 0; base < ntiles; base += kBlock) {
-        const int i = base + threadIdx.x;
-        const int v = i < ntiles ? t[i] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < kBlock; off <<= 1) {
-            const int add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-            __syncthreads();
-            s[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (i < ntiles) t[i] = carry + s[threadIdx.x] - v;
-        carry += s[kBlock - 1];
+        part[threadIdx.x] += add;
         __syncthreads();
     }
-    if (threadIdx.x == 0 && count) *count = carry;
+    int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+    for (int j = lo; j < hi; ++j) {
+        const int c = count[j];
+        count[j] = run;
+        run += c;
+    }
+    if (threadIdx.x == kBlock - 1 && n_segments) *n_segments = part[kBlock - 1];
 }
 
 // Final labels: rank of the pixel's surviving root.
-__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, const int* __restrict__ comp,
-                                                             const int* __restrict__ fin,
+__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int* comp,
                                                              const int* __restrict__ rank,
-                                                             const int* __restrict__ tile_off,
+                                                             const int* __restrict__ block_off,
                                                              int32_t* __restrict__ out) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int f = fin[comp[i]];
-    out[i] = rank[f] + tile_off[f / kScanTile];
+    const int f = find_halving(comp, i);
+    out[i] = rank[f] + block_off[f / kMergeBlock];
 }
 
 }  // namespace
 
-int scan_tiles_for(int n) { return (n + kScanTile - 1) / kScanTile; }
+int scan_tiles_for(int n) { return (n + kMergeBlock - 1) / kMergeBlock; }
 
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
                                hipStream_t s) {
     const int n = w * h;
     const int nb = (n + kBlock - 1) / kBlock;
-    int* comp = ws.ccl0;
-    int* size_fin = ws.ccl1;  // sizes, then the resolved join roots
-    int* join = ws.ccl2;
-    int* rank = ws.ccl3;      // local roots, then surviving-root flags, then their ranks
+    int* comp = ws.ccl0;  // local roots, then component roots, then join links
+    int* size = ws.ccl1;  // component sizes
+    int* rank = ws.ccl2;  // ranks of the surviving roots
+    int* lroot = ws.ccl3; // local roots (index inside the tile)
     hipError_t e;
 #define SLIC_STEP(name, ...)                                 \
     do {                                                     \
@@ -307,24 +308,20 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
         __VA_ARGS__;                                         \
         if ((e = hipGetLastError()) != hipSuccess) return e; \
     } while (0)
+    int* block_count = ws.scan;  // per-block surviving roots, then their offsets
     const dim3 tiles((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     SLIC_STEP("ccl_local",
-              ccl_local_kernel<<<tiles, kBlock, 0, s>>>(ws.labels, w, h, comp, rank, size_fin));
+              ccl_local_kernel<<<tiles, kBlock, 0, s>>>(ws.labels, w, h, comp, lroot, size));
     SLIC_STEP("ccl_border", ccl_border_kernel<<<tiles, 2 * kTile, 0, s>>>(ws.labels, w, h, comp));
-    SLIC_STEP("ccl_flatten",
-              ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(w, h, comp, rank, size_fin));
-    SLIC_STEP("ccl_join",
-              ccl_join_kernel<<<nb, kBlock, 0, s>>>(n, w, static_cast<long long>(g.S) * g.S,
-                                                    min_segment, comp, size_fin, join));
-    // the resolved roots overwrite the sizes, which are no longer needed
-    SLIC_STEP("ccl_resolve",
-              ccl_resolve_kernel<<<nb, kBlock, 0, s>>>(n, comp, join, size_fin, rank));
-    const int ntiles = scan_tiles_for(n);
-    SLIC_STEP("ccl_scan", scan_tiles_kernel<<<ntiles, kBlock, 0, s>>>(n, rank, ws.scan));
-    SLIC_STEP("ccl_scan", scan_totals_kernel<<<1, kBlock, 0, s>>>(ntiles, ws.scan, n_segments));
+    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(w, h, comp, lroot, size));
+    const int nmerge = scan_tiles_for(n);
+    SLIC_STEP("ccl_merge",
+              ccl_merge_kernel<<<nmerge, kMergeBlock, 0, s>>>(
+                  n, w, static_cast<long long>(g.S) * g.S, min_segment, comp, size, rank,
+                  block_count));
+    SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(nmerge, block_count, n_segments));
     SLIC_STEP("ccl_relabel",
-              ccl_relabel_kernel<<<nb, kBlock, 0, s>>>(n, comp, size_fin, rank, ws.scan,
-                                                       labels_out));
+              ccl_relabel_kernel<<<nb, kBlock, 0, s>>>(n, comp, rank, block_count, labels_out));
 #undef SLIC_STEP
     return hipSuccess;
 }

@@ -1,13 +1,28 @@
-// Image space conversion (Section 3): sRGB bytes -> planar FP32 CIELAB,
-// one thread per pixel.
+// Image space conversion (Section 3: sRGB bytes -> planar FP32 CIELAB, one
+// thread per pixel) fused with cluster centre initialisation (Section 3: the
+// superpixel map) and the seed perturbation of Section 2.
 //
-// Definition: sRGB decoding (IEC 61966-2-1) through a 256-entry table, the
+// Conversion: sRGB decoding (IEC 61966-2-1) through a 256-entry table, the
 // sRGB->XYZ matrix with each row divided by its sum (so the D65 white maps
-// to X = Y = Z = 1), the CIE f(t) in FP64 (cube root by Newton's method
-// above (6/29)^3, the linear segment below), then L = 116 fy - 16,
-// a = 500 (fx - fy), b = 200 (fy - fz) in FP32.  Every operation is IEEE
-// round-to-nearest in the order written; the file is compiled without FMA
-// contraction.
+// to X = Y = Z = 1), the CIE f(t) in FP64 (cube root above (6/29)^3, the
+// linear segment below), then L = 116 fy - 16, a = 500 (fx - fy),
+// b = 200 (fy - fz) in FP32.  Every operation is IEEE round-to-nearest in
+// the order written; the file is compiled without FMA contraction (the cube
+// root's fused multiply-adds are explicit).
+//
+// Seeds: the seed of cell (cx, cy) is the cell's middle pixel
+// x0 + (x1 - x0 - 1) / 2 (likewise in y), the cell spanning [x0, x1)
+// clipped to the image.  With perturbation it moves to the pixel of its 3x3
+// window with the smallest gradient (that of the SLIC paper the method builds
+// on), G = |I(x+1,y) - I(x-1,y)|^2 + |I(x,y+1) - I(x,y-1)|^2 over the Lab
+// vector with coordinates clamped to the image; the window is scanned row by
+// row and the seed moves only on a strictly smaller G.  The centre takes the
+// chosen pixel's Lab and position; its count and first accumulators are
+// cleared.
+//
+// Each workgroup converts a tile plus a two-pixel halo into LDS, stores the
+// tile, and seeds every cell whose middle pixel lies in the tile: the window
+// and the gradient's neighbours stay within two pixels of that pixel.
 #include <cmath>
 
 #include "slic_internal.h"
@@ -40,11 +55,11 @@ LabTables make_tables() {
     return t;
 }
 
-// Cube root of a normal, positive double by Newton's method on y^3 = t.
-// The exponent is split off so that the iteration runs on g in [0.5, 4):
-// t = f * 2^e, f in [0.5, 1), e = 3q + r with r in {0,1,2}, g = f * 2^r,
-// cbrt(t) = cbrt(g) * 2^q.  Quadratic seed, four steps of
-// y <- (2 y^3 + g) / (3 y^2).
+// Cube root of a normal, positive double.  The exponent is split off so the
+// iteration runs on g in [0.5, 4): t = f * 2^e, f in [0.5, 1), e = 3q + r
+// with r in {0,1,2}, g = f * 2^r, cbrt(t) = cbrt(g) * 2^q.  Newton's method
+// on the inverse cube root (no division): quadratic seed, four steps of
+// y <- y + y (1 - g y^3) / 3, then cbrt(g) = g * y * y.
 __device__ __forceinline__ double newton_cbrt(double t) {
     const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(t));
     const int e = static_cast<int>((bits >> 52) & 0x7ffull) - 1022;
@@ -53,22 +68,24 @@ __device__ __forceinline__ double newton_cbrt(double t) {
     const int r = ((e % 3) + 3) % 3;
     const int q = (e - r) / 3;
     const double g = f * static_cast<double>(1 << r);
-    const double lin = 0.6052 + 0.4255 * g;
+    const double lin = 1.405 - 0.4258 * g;
     const double g2 = g * g;
-    double y = lin - 0.04658 * g2;
+    double y = lin + 0.05965 * g2;
+    const double third = 1.0 / 3.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const double y2 = y * y;
         const double y3 = y2 * y;
-        double num = 2.0 * y3;
-        num = num + g;
-        const double den = 3.0 * y2;
-        y = num / den;
+        const double err = __builtin_fma(-g, y3, 1.0);
+        const double corr = y * err;
+        y = __builtin_fma(corr, third, y);
     }
+    double c = g * y;
+    c = c * y;
     // 2^q as a double (q is small: t lies in (0.0088, 1.1])
     const double scale =
         __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(q + 1023) << 52));
-    return y * scale;
+    return c * scale;
 }
 
 __device__ __forceinline__ float cie_f(float t) {
@@ -86,48 +103,168 @@ __device__ __forceinline__ float cie_f(float t) {
     return static_cast<float>(r);
 }
 
-constexpr int kLabBlockX = 64, kLabBlockY = 4;
-
-__global__ __launch_bounds__(kLabBlockX* kLabBlockY) void lab_kernel(
-    const uint8_t* __restrict__ rgb, int32_t w, int32_t h, int32_t pitch, int32_t channels,
-    float* __restrict__ L, float* __restrict__ A, float* __restrict__ B, LabTables tab) {
-    __shared__ float lin[256];
-    const int tid = threadIdx.y * kLabBlockX + threadIdx.x;
-    lin[tid] = tab.lin[tid];
-    __syncthreads();
-    const int x = blockIdx.x * kLabBlockX + threadIdx.x;
-    const int y = blockIdx.y * kLabBlockY + threadIdx.y;
-    if (x >= w || y >= h) return;
-    const uint8_t* p = rgb + static_cast<size_t>(y) * pitch + static_cast<size_t>(x) * channels;
+__device__ __forceinline__ void rgb_to_lab(const float* lin, const float* nm, const uint8_t* p,
+                                           float* L, float* A, float* B) {
     const float r = lin[p[0]], g = lin[p[1]], b = lin[p[2]];
-    float X = tab.nm[0] * r;
-    X = X + tab.nm[1] * g;
-    X = X + tab.nm[2] * b;
-    float Y = tab.nm[3] * r;
-    Y = Y + tab.nm[4] * g;
-    Y = Y + tab.nm[5] * b;
-    float Z = tab.nm[6] * r;
-    Z = Z + tab.nm[7] * g;
-    Z = Z + tab.nm[8] * b;
+    float X = nm[0] * r;
+    X = X + nm[1] * g;
+    X = X + nm[2] * b;
+    float Y = nm[3] * r;
+    Y = Y + nm[4] * g;
+    Y = Y + nm[5] * b;
+    float Z = nm[6] * r;
+    Z = Z + nm[7] * g;
+    Z = Z + nm[8] * b;
     const float fx = cie_f(X), fy = cie_f(Y), fz = cie_f(Z);
-    const size_t i = static_cast<size_t>(y) * w + x;
     const float l = 116.0f * fy;
-    L[i] = l - 16.0f;
+    *L = l - 16.0f;
     const float dxy = fx - fy;
-    A[i] = 500.0f * dxy;
+    *A = 500.0f * dxy;
     const float dyz = fy - fz;
-    B[i] = 200.0f * dyz;
+    *B = 200.0f * dyz;
+}
+
+__device__ __forceinline__ float norm2(float u, float v, float t) {
+    float a = u * u;
+    a = a + v * v;
+    a = a + t * t;
+    return a;
+}
+
+constexpr int kTW = 64, kTH = 32, kHalo = 2;
+constexpr int kSW = kTW + 2 * kHalo, kSH = kTH + 2 * kHalo;  // staged tile
+constexpr int kThreads = 1024;
+constexpr int kSeedsPerPass = kThreads / 9;
+
+struct LabSeedArgs {
+    const uint8_t* rgb;
+    int w, h, pitch, channels;
+    float *L, *A, *B;
+    int S, ns_c, ns_r, perturb;
+    float* cen;
+    int32_t* counts;
+    long long* sums;  // first accumulator buffer
+};
+
+__global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedArgs g, LabTables tab) {
+    __shared__ float lin[256];
+    __shared__ float sL[kSW * kSH], sA[kSW * kSH], sB[kSW * kSH];
+    __shared__ float grad[kThreads];
+    if (threadIdx.x < 256) lin[threadIdx.x] = tab.lin[threadIdx.x];
+    __syncthreads();
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+
+    // ---- convert the tile and its halo
+    for (int i = threadIdx.x; i < kSW * kSH; i += kThreads) {
+        const int x = x0 - kHalo + i % kSW, y = y0 - kHalo + i / kSW;
+        if (x < 0 || y < 0 || x >= g.w || y >= g.h) continue;
+        float l, a, b;
+        rgb_to_lab(lin, tab.nm,
+                   g.rgb + static_cast<size_t>(y) * g.pitch + static_cast<size_t>(x) * g.channels,
+                   &l, &a, &b);
+        sL[i] = l;
+        sA[i] = a;
+        sB[i] = b;
+        if (x >= x0 && x < x0 + kTW && y >= y0 && y < y0 + kTH) {
+            const size_t pi = static_cast<size_t>(y) * g.w + x;
+            g.L[pi] = l;
+            g.A[pi] = a;
+            g.B[pi] = b;
+        }
+    }
+    __syncthreads();
+
+    // ---- cells whose middle pixel lies in this tile
+    const int S = g.S;
+    auto middle = [&](int c, int extent) {
+        const int lo = c * S, hi = min(lo + S, extent);
+        return lo + (hi - lo - 1) / 2;
+    };
+    int cx0 = x0 / S, cx1 = min((x0 + kTW - 1) / S, g.ns_c - 1);
+    if (middle(cx0, g.w) < x0) ++cx0;
+    if (cx1 >= cx0 && middle(cx1, g.w) >= x0 + kTW) --cx1;
+    int cy0 = y0 / S, cy1 = min((y0 + kTH - 1) / S, g.ns_r - 1);
+    if (middle(cy0, g.h) < y0) ++cy0;
+    if (cy1 >= cy0 && middle(cy1, g.h) >= y0 + kTH) --cy1;
+    const int ncx = cx1 - cx0 + 1, ncy = cy1 - cy0 + 1;
+    if (ncx <= 0 || ncy <= 0) return;  // uniform across the workgroup
+    const int nseeds = ncx * ncy;
+    auto at = [&](int x, int y) { return (y - y0 + kHalo) * kSW + (x - x0 + kHalo); };
+    for (int base = 0; base < nseeds; base += kSeedsPerPass) {
+        const int sl = threadIdx.x / 9, pos = threadIdx.x % 9;
+        const int s = base + sl;
+        const bool active = sl < kSeedsPerPass && s < nseeds;
+        int cx = 0, cy = 0, sx = 0, sy = 0;
+        if (active) {
+            cx = cx0 + s % ncx;
+            cy = cy0 + s / ncx;
+            sx = middle(cx, g.w);
+            sy = middle(cy, g.h);
+            const int nx = sx + pos % 3 - 1, ny = sy + pos / 3 - 1;
+            float gv = __builtin_huge_valf();
+            if (g.perturb && nx >= 0 && nx < g.w && ny >= 0 && ny < g.h) {
+                const int xl = max(nx - 1, 0), xr = min(nx + 1, g.w - 1);
+                const int yu = max(ny - 1, 0), yd = min(ny + 1, g.h - 1);
+                const int il = at(xl, ny), ir = at(xr, ny), iu = at(nx, yu), id = at(nx, yd);
+                const float gx = norm2(sL[ir] - sL[il], sA[ir] - sA[il], sB[ir] - sB[il]);
+                const float gy = norm2(sL[id] - sL[iu], sA[id] - sA[iu], sB[id] - sB[iu]);
+                gv = gx + gy;
+            }
+            grad[threadIdx.x] = gv;
+        }
+        __syncthreads();
+        if (active && pos == 0) {
+            int bx = sx, by = sy;
+            if (g.perturb) {
+                const float* gw = grad + threadIdx.x;
+                float best = gw[4];  // the middle pixel
+                for (int p = 0; p < 9; ++p) {
+                    if (gw[p] < best) {  // positions outside the image hold +inf
+                        best = gw[p];
+                        bx = sx + p % 3 - 1;
+                        by = sy + p / 3 - 1;
+                    }
+                }
+            }
+            const int k = cy * g.ns_c + cx;
+            const int i = at(bx, by);
+            float4* c = reinterpret_cast<float4*>(g.cen + static_cast<size_t>(k) * kCenStride);
+            c[0] = make_float4(sL[i], sA[i], sB[i], static_cast<float>(bx));
+            c[1] = make_float4(static_cast<float>(by), 0.0f, 0.0f, 0.0f);
+            g.counts[k] = 0;
+            long long* z = g.sums + static_cast<size_t>(k) * kSumStride;
+#pragma unroll
+            for (int j = 0; j < kSumStride; ++j) z[j] = 0;
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
 
-hipError_t launch_lab(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int32_t channels,
-                      float* L, float* A, float* B, hipStream_t s) {
+hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
+                           int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
+                           hipStream_t s) {
     static const LabTables tab = make_tables();
-    dim3 block(kLabBlockX, kLabBlockY);
-    dim3 grid((w + kLabBlockX - 1) / kLabBlockX, (h + kLabBlockY - 1) / kLabBlockY);
-    KernelTimer t("lab", s);
-    lab_kernel<<<grid, block, 0, s>>>(rgb, w, h, pitch, channels, L, A, B, tab);
+    LabSeedArgs a;
+    a.rgb = rgb;
+    a.w = w;
+    a.h = h;
+    a.pitch = pitch;
+    a.channels = channels;
+    a.L = ws.L;
+    a.A = ws.A;
+    a.B = ws.B;
+    a.S = grid.S;
+    a.ns_c = grid.ns_c;
+    a.ns_r = grid.ns_r;
+    a.perturb = perturb;
+    a.cen = ws.cen;
+    a.counts = ws.counts;
+    a.sums = ws.sums;
+    dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
+    KernelTimer t("lab_seed", s);
+    lab_seed_kernel<<<g, kThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 

@@ -46,16 +46,21 @@ size_t workspace_layout(int32_t width, int32_t height, const Grid& g, Workspace*
 int scan_tiles_for(int n);
 
 // Launch wrappers (each returns the hipError_t of its launches).
-hipError_t launch_lab(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int32_t channels,
-                      float* L, float* A, float* B, hipStream_t s);
-hipError_t launch_seed(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int perturb,
-                       hipStream_t s);
+// CIELAB conversion of the image into ws.L/A/B fused with the seeding of
+// every centre (and the clearing of its count and first accumulators).
+hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
+                           int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
+                           hipStream_t s);
 // Association launch number t (0: the first, with the seeds as centres;
 // t >= 1 also completes the centre update of the previous launch).
-// ppt: pixels per thread (1, 2 or 4), or 0 to choose from the image size.
+// variant: launch shape 1..assign_variant_count(); an unsupported value
+// falls back to assign_default_variant.
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int ppt, hipStream_t s);
-int assign_pixels_per_thread(int32_t w, int32_t h);
+                         int variant, hipStream_t s);
+int assign_variant_count();
+bool assign_variant_shape(int variant, int* vec, int* rows, int* tile_w, int* tile_h);
+bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S);
+int assign_default_variant(int32_t w, int32_t h, int32_t S);
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,
                          hipStream_t s);
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
@@ -86,7 +91,7 @@ struct slic_ctx {
     slic::Workspace ws;
     hipStream_t stream;
     int device;
-    int ppt;        // association pixels per thread
+    int variant;    // association launch variant
     int64_t t;      // association launches so far
     int state;      // 0: k-means state valid, 1: connectivity done, 2: poisoned
 };

@@ -116,3 +116,25 @@ def test_no_device_is_an_error_not_a_fallback(abi):
     rc = abi.lib.slic_init(ctypes.byref(ctx), ctypes.byref(p), 4096, None, 8192, need)
     assert rc in (abi.SLIC_EHIP, abi.SLIC_EINVAL)
     assert ctx.value is None
+
+
+def test_assign_variant_table(abi):
+    n = abi.slic_assign_variants()
+    assert n >= 5
+    shapes = [abi.slic_assign_variant_info(v) for v in range(1, n + 1)]
+    for vec, rows, tw, th in shapes:
+        assert vec in (1, 4) and rows >= 1 and tw * th == 256 * vec * rows
+    with pytest.raises(abi.SlicError):
+        abi.slic_assign_variant_info(0)
+    with pytest.raises(abi.SlicError):
+        abi.slic_assign_variant_info(n + 1)
+    # 4-wide variants need S % 4 == 0 and width % 4 == 0
+    vec4 = [v for v in range(1, n + 1) if shapes[v - 1][0] == 4]
+    with pytest.raises(abi.SlicError):
+        abi.slic_set_assign_variant(642, 480, 16, vec4[0])
+    with pytest.raises(abi.SlicError):
+        abi.slic_set_assign_variant(640, 480, 6, vec4[0])
+    abi.slic_set_assign_variant(640, 480, 16, vec4[0])
+    assert abi.slic_get_assign_variant(640, 480, 16) == vec4[0]
+    abi.slic_set_assign_variant(640, 480, 16, 0)
+    assert abi.slic_get_assign_variant(640, 480, 16) != 0

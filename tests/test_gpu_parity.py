@@ -202,3 +202,65 @@ def test_error_paths(slic):
     assert e.value.code == _abi.SLIC_ESTATE
     ctx.close()
     torch.cuda.synchronize()
+
+
+def _supported_variants(slic, w, h, S):
+    out = []
+    for v in range(1, slic.slic_assign_variants() + 1):
+        try:
+            slic.slic_set_assign_variant(w, h, S, v)
+        except slic.SlicError:
+            continue
+        out.append(v)
+    slic.slic_set_assign_variant(w, h, S, 0)
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_every_variant_is_bit_exact(slic, name):
+    wl = synth.WORKLOADS[name]
+    img = synth.image_for(wl)
+    want = oracle_run(img, wl.S, wl.m, wl.iters, wl.perturb, enforce=True)
+    variants = _supported_variants(slic, wl.width, wl.height, wl.S)
+    assert 1 in variants and len(variants) >= 3
+    try:
+        for v in variants:
+            slic.slic_set_assign_variant(wl.width, wl.height, wl.S, v)
+            got = gpu_run(slic, img, wl.S, wl.m, wl.iters, wl.perturb, enforce=True)
+            assert_parity(got, want, enforce=True)
+    finally:
+        slic.slic_set_assign_variant(wl.width, wl.height, wl.S, 0)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_every_variant_on_ragged_images(slic, seed):
+    rng = np.random.default_rng(500 + seed)
+    w = int(rng.integers(1, 140)) * (4 if seed % 2 else 1)
+    h = int(rng.integers(1, 90))
+    S = int(rng.choice([1, 2, 3, 4, 8, 12, 16, 32]))
+    img = synth.voronoi_image(seed, w, h, int(rng.integers(1, 20)), 8.0)
+    want = oracle_run(img, S, 10.0, 2, True, enforce=True)
+    try:
+        for v in _supported_variants(slic, w, h, S):
+            slic.slic_set_assign_variant(w, h, S, v)
+            got = gpu_run(slic, img, S, 10.0, 2, True, enforce=True)
+            assert_parity(got, want, enforce=True)
+    finally:
+        slic.slic_set_assign_variant(w, h, S, 0)
+
+
+def test_autotune_records_a_supported_variant(slic):
+    wl = synth.WORKLOADS["c1"]
+    img = synth.image_for(wl)
+    rgb, _ = _to_dev(img)
+    p = slic.Params(wl.width, wl.height, S=wl.S, m=wl.m)
+    ws = slic.workspace_for(p)
+    try:
+        best, ms = slic.slic_autotune(p.c(), rgb.data_ptr(), 3, 2, 0, ws.data_ptr(), ws.numel())
+        assert best in _supported_variants(slic, wl.width, wl.height, wl.S) or best >= 1
+        assert ms > 0
+        assert slic.slic_get_assign_variant(wl.width, wl.height, wl.S) == best
+        got = gpu_run(slic, img, wl.S, wl.m, wl.iters, wl.perturb)
+        assert_parity(got, oracle_run(img, wl.S, wl.m, wl.iters, wl.perturb))
+    finally:
+        slic.slic_set_assign_variant(wl.width, wl.height, wl.S, 0)

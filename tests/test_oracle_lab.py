@@ -51,7 +51,7 @@ def test_cbrt_newton_against_library():
     t = np.concatenate([rng.uniform(216 / 24389, 1.1, 20000), np.geomspace(1e-300, 1e300, 2000)])
     got = np.array([oracle.cbrt(x) for x in t])
     ref = np.cbrt(t)
-    assert np.all(np.abs(got - ref) <= 2 * np.spacing(ref))
+    assert np.all(np.abs(got - ref) <= 4 * np.spacing(ref))
     assert oracle.cbrt(1.0) == 1.0
     for x, r in [(8.0, 2.0), (0.125, 0.5), (27.0, 3.0), (0.001, 0.1)]:
         assert abs(oracle.cbrt(x) - r) <= np.spacing(r)

@@ -22,7 +22,7 @@ MUTANTS = [
     ("a_sign", "float dxy = fx - fy;", "float dxy = fy - fx;", ["lab"]),
     ("matrix_swap", "{0.4124, 0.3576, 0.1805}", "{0.4124, 0.1805, 0.3576}", ["lab"]),
     ("linear_segment", "r = s / 116.0;", "r = s / 161.0;", ["lab"]),
-    ("cbrt_step", "double den = 3.0 * y2;", "double den = 3.01 * y2;", ["lab"]),
+    ("cbrt_step", "double err = fma(-g, y3, 1.0);", "double err = fma(-g, y3, 1.001);", ["lab"]),
     ("gradient_dropped_term", "B[d] - B[u]", "B[d] - B[d]", ["seed"]),
     ("gradient_clamp", "xl = x > 0 ? x - 1 : 0", "xl = x > 0 ? x - 1 : 1", ["seed"]),
     ("seed_tiebreak", "if (g < gbest)", "if (g <= gbest)", ["seed"]),
