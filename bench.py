@@ -109,6 +109,73 @@ def kernel_times(slic, torch, frame: Frame, steps: int, iters: int, enforce: boo
     return out
 
 
+def bench_c4(slic, torch, dev, reps: int):
+    """Workload c4: 64 uneven images through one batch plan (autotuned, one
+    HIP graph per run) against 64 sequential slic_segment calls."""
+    import synth
+    wls = synth.batch_workload()
+    imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in wls]
+    params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb) for w in wls]
+    iters = wls[0].iters
+    b = slic.Batch(params, imgs, iters, use_graph=True)
+    variant, _ = b.autotune(reps=2)
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    # per-launch association time, from a run without the graph
+    nb = slic.Batch(params, imgs, iters, variant=variant, use_graph=False)
+    nb.run()
+    torch.cuda.synchronize()
+    slic.slic_timing_enable(True)
+    for _ in range(reps):
+        nb.run()
+    torch.cuda.synchronize()
+    slic.slic_timing_enable(False)
+    a_ms, a_n = slic.slic_timing_read("assign")
+    nb.close()
+    # sequential per-image calls, each with its own autotuned variant
+    frames = []
+    for w, img in zip(wls, imgs):
+        f = Frame.__new__(Frame)
+        f.slic, f.wl, f.rgb = slic, w, img
+        f.p = params[len(frames)]
+        f.cp = f.p.c()
+        f.ws = slic.workspace_for(f.p, dev)
+        f.labels = torch.empty((w.height, w.width), dtype=torch.int32, device=dev)
+        f.nseg = torch.empty(1, dtype=torch.int32, device=dev)
+        f.stream = torch.cuda.current_stream().cuda_stream
+        f.variant, _ = slic.slic_autotune(f.cp, img.data_ptr(), 3, 2, f.stream, f.ws.data_ptr(),
+                                          f.ws.numel())
+        frames.append(f)
+    for f in frames:
+        f.run(iters, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for f in frames:
+            f.run(iters, False)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    b.close()
+    npx = sum(w.n_pixels for w in wls)
+    nbytes = sum(assign_bytes(w.n_pixels, p.n_clusters) for w, p in zip(wls, params))
+    avg = a_ms / max(a_n, 1)
+    return {"images": len(wls), "mpix": round(npx / 1e6, 2), "iters": iters,
+            "variant": variant, "batch_graph_ms": round(t_batch * 1e3, 3),
+            "sequential_ms": round(t_seq * 1e3, 3),
+            "images_per_s": round(len(wls) / t_batch, 1),
+            "speedup_vs_sequential": round(t_seq / t_batch, 2),
+            "assign_avg_us": round(avg * 1e3, 2),
+            "mpix_per_s_per_iter": round(npx / (avg * 1e-3) / 1e6, 1),
+            "assign_gbps": round(nbytes / (avg * 1e-3) / 1e9, 1),
+            "assign_hbm_frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
 def traffic_from_profile():
     """HBM bytes per association launch from the committed PMC summary, or
     None if it is missing or the kernel source changed since."""
@@ -228,6 +295,7 @@ def main() -> int:
                 entry["assign_gbps"] = round(b / (a * 1e-3) / 1e9, 1)
                 entry["assign_hbm_frac"] = round(b / (a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             extra[name] = entry
+        extra["c4"] = bench_c4(slic, torch, dev, reps=max(5, args.steps // 50))
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -149,6 +149,40 @@ int slic_autotune(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, i
                   void* hip_stream, void* d_ws, size_t ws_bytes, int32_t* best_variant,
                   float* best_ms_per_iter);
 
+/* Batches: many images of uneven sizes and grid steps segmented together.
+ * Every launch of the pipeline covers all images: one conversion+seeding
+ * launch, 1 + n_iters association launches (workgroups walk a table of
+ * (image, tile) pairs), then, with `enforce`, connectivity per image.  The
+ * results equal n_images separate slic_segment calls bit for bit.
+ *  - slic_batch_workspace_bytes: device workspace for the batch (every
+ *    image's own workspace plus the tile tables); 0 if any params invalid.
+ *  - slic_batch_create: validates every image, lays out the workspace,
+ *    uploads the tables (synchronous host-to-device copies) and, if
+ *    use_graph, captures the whole pipeline into a HIP graph.  `variant` is
+ *    an association variant every image supports, or 0 for the largest such
+ *    tile.  d_rgb[i], d_labels[i] (int32[H_i*W_i]) and d_n_segments
+ *    (int32[n_images], may be NULL, written only with enforce) are the
+ *    caller's device buffers and must stay valid while the batch exists.
+ *  - slic_batch_run: enqueues the pipeline on hip_stream (one graph launch
+ *    with use_graph).  May be called repeatedly (the images are re-read).
+ *  - slic_batch_autotune: times `reps` runs per variant that every image
+ *    supports, keeps the fastest (re-capturing the graph) and returns it with
+ *    its time per run in milliseconds.  Synchronises the host.
+ *  - slic_segment_batch: create (no graph), run, destroy in one call. */
+typedef struct slic_batch slic_batch;
+size_t slic_batch_workspace_bytes(const slic_params* per_image, int32_t n_images);
+int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_images,
+                      const uint8_t* const* d_rgb, int32_t* const* d_labels, int32_t n_iters,
+                      int32_t enforce, int32_t* d_n_segments, int32_t variant, int32_t use_graph,
+                      void* d_ws, size_t ws_bytes);
+int slic_batch_run(slic_batch* b, void* hip_stream);
+int slic_batch_autotune(slic_batch* b, void* hip_stream, int32_t reps, int32_t* best_variant,
+                        float* best_ms);
+void slic_batch_destroy(slic_batch* b);
+int slic_segment_batch(const slic_params* per_image, const uint8_t* const* d_rgb, int32_t n_images,
+                       int32_t n_iters, int32_t enforce, int32_t* const* d_labels,
+                       int32_t* d_n_segments, void* hip_stream, void* d_ws, size_t ws_bytes);
+
 /* Kernel timing for measurement.  slic_timing_enable(1) forgets earlier
  * records and starts recording: every kernel launch of the library is then
  * bracketed by HIP events on the stream it is launched on.

@@ -13,14 +13,17 @@ import torch
 from . import _abi
 from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, SLIC_OK,
                    SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_assign_variant_info,
-                   slic_assign_variants, slic_autotune, slic_destroy,
+                   slic_assign_variants, slic_autotune, slic_batch_autotune, slic_batch_create,
+                   slic_batch_destroy, slic_batch_run, slic_batch_workspace_bytes,
+                   slic_destroy, slic_segment_batch,
                    slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
                    slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
                    slic_iterate, slic_segment, slic_set_assign_variant, slic_strerror,
                    slic_timing_enable, slic_timing_read, slic_workspace_bytes)
 
 __all__ = [
-    "Params", "Context", "segment", "workspace_for", "SlicError", "SlicParams", *EXPORTED,
+    "Params", "Context", "Batch", "segment", "workspace_for", "SlicError", "SlicParams",
+    *EXPORTED,
 ]
 
 
@@ -146,3 +149,45 @@ def segment(rgb: torch.Tensor, p: Params, iters: int, enforce: bool = False,
                  ptr("centres"), ptr("energy"), ptr("n_segments"), _stream(stream), ws.data_ptr(),
                  ws.numel())
     return out
+
+
+class Batch:
+    """A slic_batch: many images segmented by shared launches (optionally one
+    HIP graph).  ``images`` are uint8 device tensors of H*W*channels bytes;
+    the label tensors are allocated here and filled by every ``run``."""
+
+    def __init__(self, params, images, iters: int, enforce: bool = False, variant: int = 0,
+                 use_graph: bool = True, device=None):
+        if len(params) != len(images) or not params:
+            raise ValueError("one Params per image")
+        for p, img in zip(params, images):
+            _check_rgb(img, p)
+        dev = device or images[0].device
+        self.params = list(params)
+        self._cp = [p.c() for p in params]
+        self._images = list(images)
+        self.labels = [torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
+                       for p in params]
+        self.n_segments = torch.empty(len(params), dtype=torch.int32, device=dev) if enforce \
+            else None
+        n = slic_batch_workspace_bytes(self._cp)
+        self.ws = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.batch = slic_batch_create(
+            self._cp, [t.data_ptr() for t in images], [t.data_ptr() for t in self.labels], iters,
+            1 if enforce else 0, self.n_segments.data_ptr() if enforce else None, variant,
+            1 if use_graph else 0, self.ws.data_ptr(), self.ws.numel())
+
+    def run(self, stream=None) -> "Batch":
+        slic_batch_run(self.batch, _stream(stream))
+        return self
+
+    def autotune(self, reps: int = 3, stream=None):
+        return slic_batch_autotune(self.batch, _stream(stream), reps)
+
+    def close(self) -> None:
+        if getattr(self, "batch", None):
+            slic_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        self.close()

@@ -58,6 +58,13 @@ _SIGS = {
     "slic_set_assign_variant": ([_I, _I, _I, _I], ctypes.c_int),
     "slic_get_assign_variant": ([_I, _I, _I, _P], ctypes.c_int),
     "slic_autotune": ([_PP, _P, _I, _I, _P, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
+    "slic_batch_workspace_bytes": ([_PP, _I], ctypes.c_size_t),
+    "slic_batch_create": ([ctypes.POINTER(_P), _PP, _I, _P, _P, _I, _I, _P, _I, _I, _P,
+                           ctypes.c_size_t], ctypes.c_int),
+    "slic_batch_run": ([_P, _P], ctypes.c_int),
+    "slic_batch_autotune": ([_P, _P, _I, _P, _P], ctypes.c_int),
+    "slic_batch_destroy": ([_P], None),
+    "slic_segment_batch": ([_PP, _P, _I, _I, _I, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_timing_enable": ([_I], ctypes.c_int),
     "slic_timing_read": ([ctypes.c_char_p, _P, _P], ctypes.c_int),
 }
@@ -163,6 +170,56 @@ def slic_autotune(p: SlicParams, d_rgb: int, n_iters: int, reps: int, stream: in
     _check(lib.slic_autotune(ctypes.byref(p), d_rgb, n_iters, reps, stream, d_ws, ws_bytes,
                              ctypes.byref(best), ctypes.byref(ms)), "slic_autotune")
     return int(best.value), float(ms.value)
+
+
+def _params_array(params):
+    arr = (SlicParams * len(params))(*params)
+    return arr
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+
+def slic_batch_workspace_bytes(params) -> int:
+    arr = _params_array(params)
+    n = lib.slic_batch_workspace_bytes(arr, len(params))
+    if n == 0:
+        raise SlicError(SLIC_EINVAL, "slic_batch_workspace_bytes")
+    return int(n)
+
+
+def slic_batch_create(params, d_rgb, d_labels, n_iters: int, enforce: int, d_n_segments,
+                      variant: int, use_graph: int, d_ws: int, ws_bytes: int) -> int:
+    b = _P()
+    _check(lib.slic_batch_create(ctypes.byref(b), _params_array(params), len(params),
+                                 _ptr_array(d_rgb), _ptr_array(d_labels), n_iters, enforce,
+                                 d_n_segments, variant, use_graph, d_ws, ws_bytes),
+           "slic_batch_create")
+    return int(b.value)
+
+
+def slic_batch_run(batch: int, stream: int) -> None:
+    _check(lib.slic_batch_run(batch, stream), "slic_batch_run")
+
+
+def slic_batch_autotune(batch: int, stream: int, reps: int):
+    best = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(lib.slic_batch_autotune(batch, stream, reps, ctypes.byref(best), ctypes.byref(ms)),
+           "slic_batch_autotune")
+    return int(best.value), float(ms.value)
+
+
+def slic_batch_destroy(batch: int) -> None:
+    lib.slic_batch_destroy(batch)
+
+
+def slic_segment_batch(params, d_rgb, n_iters: int, enforce: int, d_labels, d_n_segments,
+                       stream: int, d_ws: int, ws_bytes: int) -> None:
+    _check(lib.slic_segment_batch(_params_array(params), _ptr_array(d_rgb), len(params), n_iters,
+                                  enforce, _ptr_array(d_labels), d_n_segments, stream, d_ws,
+                                  ws_bytes), "slic_segment_batch")
 
 
 def slic_timing_enable(on: bool) -> None:

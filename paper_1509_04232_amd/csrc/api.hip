@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -42,6 +43,8 @@ bool timing_enabled() { return g_timing; }
 
 KernelTimer::KernelTimer(const char* name, hipStream_t s) : name_(name), s_(s), start_(nullptr) {
     if (!g_timing) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     hipEvent_t e = take_event();
     if (e && hipEventRecord(e, s) == hipSuccess) start_ = e;
 }
@@ -206,6 +209,181 @@ void bind(slic_ctx* c, const slic_params* p, void* d_ws, void* stream) {
     c->variant = resolve_variant(p->width, p->height, c->g.S);
     c->t = 0;
     c->device = 0;
+}
+
+}  // namespace
+}  // namespace slic
+
+// ------------------------------------------------------------------ batch
+
+struct slic_batch {
+    int n = 0;
+    std::vector<slic_params> params;
+    std::vector<slic::Grid> grids;
+    std::vector<slic::Workspace> ws;
+    std::vector<const uint8_t*> rgb;
+    std::vector<int32_t*> labels;
+    int32_t* n_segments = nullptr;
+    int n_iters = 0, enforce = 0, variant = 0, use_graph = 0;
+    int min_S = 0;
+    // device tables inside the caller's workspace
+    slic::LabSeedImage* lab_images = nullptr;
+    int* lab_tile_image = nullptr;
+    int* lab_tile_first = nullptr;
+    int lab_tiles = 0;
+    slic::AssignImage* asg_images = nullptr;
+    int* asg_tile_image = nullptr;
+    int* asg_tile_first = nullptr;
+    int asg_tiles = 0, asg_tiles_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int state = 0;  // 0 ok, 2 poisoned
+};
+
+namespace slic {
+namespace {
+
+int batch_variant_ok(const slic_batch* b, int v) {
+    for (int i = 0; i < b->n; ++i)
+        if (!assign_variant_supported(v, b->params[i].width, b->params[i].height, b->grids[i].S))
+            return 0;
+    return 1;
+}
+
+// Bytes of the batch workspace: every image's own workspace, then the tables.
+size_t batch_layout(const slic_params* p, int32_t n, slic_batch* b, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* q = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return q;
+    };
+    int lab_tiles = 0, asg_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        Grid g;
+        compute_grid(p + i, &g);
+        Workspace w{};
+        const size_t bytes = workspace_layout(p[i].width, p[i].height, g, &w, nullptr);
+        char* region = take(bytes);
+        if (b) {
+            workspace_layout(p[i].width, p[i].height, g, &w, region);
+            b->grids.push_back(g);
+            b->ws.push_back(w);
+        }
+        lab_tiles += ((p[i].width + lab_seed_tile_w() - 1) / lab_seed_tile_w()) *
+                     ((p[i].height + lab_seed_tile_h() - 1) / lab_seed_tile_h());
+        int most = 0;  // the variant with the smallest tiles has the most
+        for (int v = 1; v <= assign_variant_count(); ++v) {
+            int tx = 0, ty = 0;
+            assign_tiles(v, p[i].width, p[i].height, &tx, &ty);
+            most = std::max(most, tx * ty);
+        }
+        asg_cap += most;
+    }
+    char* li = take(sizeof(LabSeedImage) * n);
+    char* lt = take(sizeof(int) * lab_tiles);
+    char* lf = take(sizeof(int) * n);
+    char* ai = take(sizeof(AssignImage) * n);
+    char* at = take(sizeof(int) * asg_cap);
+    char* af = take(sizeof(int) * n);
+    if (b) {
+        b->lab_images = reinterpret_cast<LabSeedImage*>(li);
+        b->lab_tile_image = reinterpret_cast<int*>(lt);
+        b->lab_tile_first = reinterpret_cast<int*>(lf);
+        b->lab_tiles = lab_tiles;
+        b->asg_images = reinterpret_cast<AssignImage*>(ai);
+        b->asg_tile_image = reinterpret_cast<int*>(at);
+        b->asg_tile_first = reinterpret_cast<int*>(af);
+        b->asg_tiles_cap = asg_cap;
+    }
+    return off;
+}
+
+// Upload the association tables for variant v (synchronous copies).
+hipError_t batch_upload_assign(slic_batch* b, int v) {
+    std::vector<AssignImage> imgs(b->n);
+    std::vector<int> first(b->n), tile_image;
+    for (int i = 0; i < b->n; ++i) {
+        imgs[i] = assign_image(b->ws[i], b->params[i].width, b->params[i].height, b->grids[i], v);
+        int tx = 0, ty = 0;
+        assign_tiles(v, b->params[i].width, b->params[i].height, &tx, &ty);
+        first[i] = static_cast<int>(tile_image.size());
+        tile_image.insert(tile_image.end(), static_cast<size_t>(tx) * ty, i);
+    }
+    b->asg_tiles = static_cast<int>(tile_image.size());
+    b->variant = v;
+    hipError_t e = hipMemcpy(b->asg_images, imgs.data(), sizeof(AssignImage) * b->n,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->asg_tile_image, tile_image.data(), sizeof(int) * tile_image.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->asg_tile_first, first.data(), sizeof(int) * b->n, hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t batch_upload_lab(slic_batch* b) {
+    std::vector<LabSeedImage> imgs(b->n);
+    std::vector<int> first(b->n), tile_image;
+    for (int i = 0; i < b->n; ++i) {
+        const slic_params& p = b->params[i];
+        imgs[i] = lab_seed_image(b->rgb[i], p.width, p.height, p.pitch, p.channels, b->ws[i],
+                                 b->grids[i], (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0);
+        const int tiles = imgs[i].tiles_x * ((p.height + lab_seed_tile_h() - 1) / lab_seed_tile_h());
+        first[i] = static_cast<int>(tile_image.size());
+        tile_image.insert(tile_image.end(), static_cast<size_t>(tiles), i);
+    }
+    hipError_t e = hipMemcpy(b->lab_images, imgs.data(), sizeof(LabSeedImage) * b->n,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->lab_tile_image, tile_image.data(), sizeof(int) * tile_image.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->lab_tile_first, first.data(), sizeof(int) * b->n, hipMemcpyHostToDevice);
+    return e;
+}
+
+// The whole pipeline for every image: one conversion+seeding launch,
+// 1 + n_iters association launches, then connectivity per image.
+hipError_t batch_enqueue(const slic_batch* b, hipStream_t s) {
+    const LabSeedTileMap lmap{b->lab_images, b->lab_tile_image, b->lab_tile_first};
+    hipError_t e = launch_lab_seed_batch(lmap, b->lab_tiles, s);
+    const AssignTileMap amap{b->asg_images, b->asg_tile_image, b->asg_tile_first};
+    for (int t = 0; e == hipSuccess && t <= b->n_iters; ++t)
+        e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, s);
+    for (int i = 0; e == hipSuccess && b->enforce && i < b->n; ++i) {
+        Workspace w = b->ws[i];
+        w.labels = b->labels[i];
+        e = launch_connectivity(w, b->params[i].width, b->params[i].height, b->grids[i],
+                                b->params[i].min_segment, b->labels[i],
+                                b->n_segments ? b->n_segments + i : nullptr, s);
+    }
+    return e;
+}
+
+void batch_drop_graph(slic_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Capture the pipeline into a graph on a private default-priority stream.
+hipError_t batch_capture(slic_batch* b) {
+    batch_drop_graph(b);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t ee = batch_enqueue(b, cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (ee != hipSuccess) e = ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) batch_drop_graph(b);
+    return e;
 }
 
 }  // namespace
@@ -425,6 +603,142 @@ const char* slic_strerror(int code) {
         case SLIC_ESTATE: return "invalid context state";
         default: return "unknown error";
     }
+}
+
+size_t slic_batch_workspace_bytes(const slic_params* per_image, int32_t n_images) {
+    if (!per_image || n_images < 1) return 0;
+    for (int i = 0; i < n_images; ++i)
+        if (!params_ok(per_image + i)) return 0;
+    return batch_layout(per_image, n_images, nullptr, nullptr);
+}
+
+int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_images,
+                      const uint8_t* const* d_rgb, int32_t* const* d_labels, int32_t n_iters,
+                      int32_t enforce, int32_t* d_n_segments, int32_t variant, int32_t use_graph,
+                      void* d_ws, size_t ws_bytes) {
+    if (!out || !per_image || n_images < 1 || !d_rgb || !d_labels || n_iters < 0 || !d_ws ||
+        !aligned(d_ws))
+        return SLIC_EINVAL;
+    *out = nullptr;
+    const size_t need = slic_batch_workspace_bytes(per_image, n_images);
+    if (need == 0 || ws_bytes < need) return SLIC_EINVAL;
+    for (int i = 0; i < n_images; ++i)
+        if (!d_rgb[i] || !d_labels[i]) return SLIC_EINVAL;
+    int rc = check_device_ptr(d_ws);
+    for (int i = 0; rc == SLIC_OK && i < n_images; ++i) {
+        rc = check_device_ptr(d_rgb[i]);
+        if (rc == SLIC_OK) rc = check_device_ptr(d_labels[i]);
+    }
+    if (rc == SLIC_OK && d_n_segments) rc = check_device_ptr(d_n_segments);
+    if (rc) return rc;
+    slic_batch* b = new (std::nothrow) slic_batch;
+    if (!b) return SLIC_ENOMEM;
+    b->n = n_images;
+    b->params.assign(per_image, per_image + n_images);
+    b->rgb.assign(d_rgb, d_rgb + n_images);
+    b->labels.assign(d_labels, d_labels + n_images);
+    b->n_segments = d_n_segments;
+    b->n_iters = n_iters;
+    b->enforce = enforce ? 1 : 0;
+    b->use_graph = use_graph ? 1 : 0;
+    batch_layout(per_image, n_images, b, static_cast<char*>(d_ws));
+    b->min_S = b->grids[0].S;
+    for (int i = 0; i < n_images; ++i) {
+        b->min_S = std::min(b->min_S, b->grids[i].S);
+        b->ws[i].labels = b->labels[i];  // associate straight into the caller's buffers
+    }
+    if (variant != 0 && !batch_variant_ok(b, variant)) {
+        delete b;
+        return SLIC_EINVAL;
+    }
+    if (variant == 0) {  // largest tiles every image supports
+        for (int v = assign_variant_count(); v >= 1 && variant == 0; --v)
+            if (batch_variant_ok(b, v)) variant = v;
+    }
+    hipError_t e = batch_upload_lab(b);
+    if (e == hipSuccess) e = batch_upload_assign(b, variant);
+    if (e == hipSuccess && b->use_graph) e = batch_capture(b);
+    if (e != hipSuccess) {
+        batch_drop_graph(b);
+        delete b;
+        return SLIC_EHIP;
+    }
+    *out = b;
+    return SLIC_OK;
+}
+
+int slic_batch_run(slic_batch* b, void* hip_stream) {
+    if (!b) return SLIC_EINVAL;
+    if (b->state != 0) return SLIC_ESTATE;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e = b->exec ? hipGraphLaunch(b->exec, s) : batch_enqueue(b, s);
+    if (e != hipSuccess) {
+        b->state = 2;
+        return SLIC_EHIP;
+    }
+    return SLIC_OK;
+}
+
+int slic_batch_autotune(slic_batch* b, void* hip_stream, int32_t reps, int32_t* best_variant,
+                        float* best_ms) {
+    if (!b || reps < 1) return SLIC_EINVAL;
+    if (b->state != 0) return SLIC_ESTATE;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SLIC_EHIP;
+    int best = 0;
+    float best_t = 0.0f;
+    hipError_t e = hipStreamSynchronize(s);
+    for (int v = 1; e == hipSuccess && v <= assign_variant_count(); ++v) {
+        if (!batch_variant_ok(b, v)) continue;
+        e = batch_upload_assign(b, v);
+        if (e == hipSuccess && b->use_graph) e = batch_capture(b);
+        float total = 0.0f;
+        for (int r = 0; e == hipSuccess && r <= reps; ++r) {  // the first round warms up
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = b->exec ? hipGraphLaunch(b->exec, s) : batch_enqueue(b, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) total += ms;
+        }
+        if (e == hipSuccess && (best == 0 || total / reps < best_t)) {
+            best = v;
+            best_t = total / reps;
+        }
+    }
+    if (e == hipSuccess && best != 0) {
+        e = batch_upload_assign(b, best);
+        if (e == hipSuccess && b->use_graph) e = batch_capture(b);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        b->state = 2;
+        return SLIC_EHIP;
+    }
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
+    return SLIC_OK;
+}
+
+void slic_batch_destroy(slic_batch* b) {
+    if (!b) return;
+    batch_drop_graph(b);
+    delete b;
+}
+
+int slic_segment_batch(const slic_params* per_image, const uint8_t* const* d_rgb, int32_t n_images,
+                       int32_t n_iters, int32_t enforce, int32_t* const* d_labels,
+                       int32_t* d_n_segments, void* hip_stream, void* d_ws, size_t ws_bytes) {
+    slic_batch* b = nullptr;
+    int rc = slic_batch_create(&b, per_image, n_images, d_rgb, d_labels, n_iters, enforce,
+                               d_n_segments, 0, 0, d_ws, ws_bytes);
+    if (rc) return rc;
+    rc = slic_batch_run(b, hip_stream);
+    slic_batch_destroy(b);
+    return rc;
 }
 
 int slic_timing_enable(int32_t on) {

@@ -93,19 +93,22 @@ __device__ __noinline__ int reference_slot(const float4* cen4, const float* ceny
     return sref;
 }
 
-struct AssignArgs {
-    const float* L;
-    const float* A;
-    const float* B;
-    int w, h, S, ns_c, ns_r;
-    float wgt;
-    float* cen;            // K x kCenStride: centres used by the last launch
-    int32_t* counts;       // K
-    int32_t* labels;       // N
-    long long* sums_prev;  // read (mean half), or null on the first launch
-    long long* sums_acc;   // accumulated by this launch
-    long long* sums_next;  // cleared by this launch (owners)
-};
+// A workgroup's image: from the kernel argument (one image) or, for a batch,
+// from the image table through the tile-to-image map.
+__device__ __forceinline__ void resolve_image(const AssignImage& single, const AssignTileMap& map,
+                                              AssignImage* g, int* bx, int* by) {
+    if (map.images) {
+        const int img = map.tile_image[blockIdx.x];
+        *g = map.images[img];
+        const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
+        *bx = local % g->tiles_x;
+        *by = local / g->tiles_x;
+    } else {
+        *g = single;
+        *bx = blockIdx.x;
+        *by = blockIdx.y;
+    }
+}
 
 // Shared-memory layout (dynamic): for every cell of the staged window
 // (the workgroup's cells plus a one-cell ring, out-of-grid cells included):
@@ -137,10 +140,19 @@ __device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, in
 }
 
 template <int VEC, int ROWS>
-__global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
+__global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, AssignTileMap map,
+                                                          long long t) {
     using Sh = Shape<VEC, ROWS>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int x0 = blockIdx.x * Sh::kTileW, y0 = blockIdx.y * Sh::kTileH;
+    AssignImage g;
+    int bx, by;
+    resolve_image(single, map, &g, &bx, &by);
+    const size_t ring = static_cast<size_t>(g.K) * kSumStride;
+    long long* const sums_acc = g.sums + ring * static_cast<size_t>(t % 3);
+    const long long* const sums_prev =
+        t > 0 ? g.sums + ring * static_cast<size_t>((t + 2) % 3) : nullptr;
+    long long* const sums_next = g.sums + ring * static_cast<size_t>((t + 1) % 3);
+    const int x0 = bx * Sh::kTileW, y0 = by * Sh::kTileH;
     const int tx = threadIdx.x % Sh::kTX, ty = threadIdx.x / Sh::kTX;
     const int x = x0 + tx * VEC;
     const bool col_ok = x < g.w;
@@ -195,13 +207,12 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
         }
         const int k = cy * g.ns_c + cx;
         kidx[i] = k;
-        const bool owner = (cx * S) / Sh::kTileW == static_cast<int>(blockIdx.x) &&
-                           (cy * S) / Sh::kTileH == static_cast<int>(blockIdx.y);
+        const bool owner = (cx * S) / Sh::kTileW == bx && (cy * S) / Sh::kTileH == by;
         float* c = g.cen + static_cast<size_t>(k) * kCenStride;
         float4 v;
         float vy;
-        if (g.sums_prev) {
-            const long long* s = g.sums_prev + static_cast<size_t>(k) * kSumStride;
+        if (sums_prev) {
+            const long long* s = sums_prev + static_cast<size_t>(k) * kSumStride;
             const long long n = s[5];
             if (n > 0) {
                 const double dn = static_cast<double>(n);
@@ -227,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
             vy = c[4];
         }
         if (owner) {
-            long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
+            long long* z = sums_next + static_cast<size_t>(k) * kSumStride;
             for (int j = 0; j < kSumStride; ++j) z[j] = 0;
         }
         cen4[i] = v;
@@ -328,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignArgs g) {
         const long long sx = static_cast<long long>(p & 0xFFFFFull) + n * x0;
         const long long sy = static_cast<long long>((p >> 20) & 0xFFFFFull) + n * y0;
         unsigned long long* s =
-            reinterpret_cast<unsigned long long*>(g.sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
+            reinterpret_cast<unsigned long long*>(sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
         atomicAdd(s + 0, bins[i]);
         atomicAdd(s + 1, bins[ncells + i]);
         atomicAdd(s + 2, bins[2 * ncells + i]);
@@ -396,18 +407,25 @@ size_t variant_lds(int S) {
 }
 
 template <int VEC, int ROWS>
-hipError_t launch_variant(const AssignArgs& a, hipStream_t s) {
+hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int total_tiles,
+                          int min_S, long long t, hipStream_t s) {
     using Sh = Shape<VEC, ROWS>;
-    dim3 grid((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
-    KernelTimer t("assign", s);
-    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(a.S), s>>>(a);
+    dim3 grid;
+    if (map.images) {
+        grid = dim3(total_tiles);
+    } else {
+        grid = dim3((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
+    }
+    KernelTimer timer("assign", s);
+    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t);
     return hipGetLastError();
 }
 
 struct VariantDesc {
     int vec, rows;
     size_t (*lds)(int);
-    hipError_t (*launch)(const AssignArgs&, hipStream_t);
+    hipError_t (*launch)(const AssignImage&, const AssignTileMap&, int, int, long long,
+                         hipStream_t);
 };
 
 const VariantDesc kVariants[] = {
@@ -452,9 +470,16 @@ int assign_default_variant(int32_t w, int32_t h, int32_t S) {
     return v;
 }
 
-hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int variant, hipStream_t s) {
-    AssignArgs a;
+bool assign_tiles(int variant, int32_t w, int32_t h, int* tiles_x, int* tiles_y) {
+    int tw = 0, th = 0;
+    if (!assign_variant_shape(variant, nullptr, nullptr, &tw, &th)) return false;
+    if (tiles_x) *tiles_x = (w + tw - 1) / tw;
+    if (tiles_y) *tiles_y = (h + th - 1) / th;
+    return true;
+}
+
+AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant) {
+    AssignImage a;
     a.L = ws.L;
     a.A = ws.A;
     a.B = ws.B;
@@ -463,16 +488,30 @@ hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     a.S = g.S;
     a.ns_c = g.ns_c;
     a.ns_r = g.ns_r;
+    a.K = g.K;
     a.wgt = g.w;
     a.cen = ws.cen;
     a.counts = ws.counts;
     a.labels = ws.labels;
-    const size_t stride = static_cast<size_t>(g.K) * kSumStride;
-    a.sums_acc = ws.sums + stride * static_cast<size_t>(t % 3);
-    a.sums_prev = t > 0 ? ws.sums + stride * static_cast<size_t>((t + 2) % 3) : nullptr;
-    a.sums_next = ws.sums + stride * static_cast<size_t>((t + 1) % 3);
+    a.sums = ws.sums;
+    a.tiles_x = 0;
+    assign_tiles(variant, w, h, &a.tiles_x, nullptr);
+    return a;
+}
+
+hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
+                         int variant, hipStream_t s) {
     if (!assign_variant_supported(variant, w, h, g.S)) variant = assign_default_variant(w, h, g.S);
-    return kVariants[variant - 1].launch(a, s);
+    const AssignImage a = assign_image(ws, w, h, g, variant);
+    const AssignTileMap none{nullptr, nullptr, nullptr};
+    return kVariants[variant - 1].launch(a, none, 0, g.S, t, s);
+}
+
+hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
+                               int variant, hipStream_t s) {
+    if (variant < 1 || variant > kNumVariants || !map.images) return hipErrorInvalidValue;
+    AssignImage unused{};
+    return kVariants[variant - 1].launch(unused, map, total_tiles, min_S, t, s);
 }
 
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,

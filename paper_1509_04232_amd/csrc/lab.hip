@@ -136,23 +136,27 @@ constexpr int kSW = kTW + 2 * kHalo, kSH = kTH + 2 * kHalo;  // staged tile
 constexpr int kThreads = 1024;
 constexpr int kSeedsPerPass = kThreads / 9;
 
-struct LabSeedArgs {
-    const uint8_t* rgb;
-    int w, h, pitch, channels;
-    float *L, *A, *B;
-    int S, ns_c, ns_r, perturb;
-    float* cen;
-    int32_t* counts;
-    long long* sums;  // first accumulator buffer
-};
-
-__global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedArgs g, LabTables tab) {
+__global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single, LabSeedTileMap map,
+                                                            LabTables tab) {
     __shared__ float lin[256];
     __shared__ float sL[kSW * kSH], sA[kSW * kSH], sB[kSW * kSH];
     __shared__ float grad[kThreads];
     if (threadIdx.x < 256) lin[threadIdx.x] = tab.lin[threadIdx.x];
+    LabSeedImage g;
+    int bx, by;
+    if (map.images) {  // batch: this workgroup's image from the tile map
+        const int img = map.tile_image[blockIdx.x];
+        g = map.images[img];
+        const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
+        bx = local % g.tiles_x;
+        by = local / g.tiles_x;
+    } else {
+        g = single;
+        bx = blockIdx.x;
+        by = blockIdx.y;
+    }
     __syncthreads();
-    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+    const int x0 = bx * kTW, y0 = by * kTH;
 
     // ---- convert the tile and its halo
     for (int i = threadIdx.x; i < kSW * kSH; i += kThreads) {
@@ -240,13 +244,19 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedArgs g, LabTa
     }
 }
 
+const LabTables& tables() {
+    static const LabTables tab = make_tables();
+    return tab;
+}
+
 }  // namespace
 
-hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
-                           int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
-                           hipStream_t s) {
-    static const LabTables tab = make_tables();
-    LabSeedArgs a;
+int lab_seed_tile_w() { return kTW; }
+int lab_seed_tile_h() { return kTH; }
+
+LabSeedImage lab_seed_image(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
+                            int32_t channels, const Workspace& ws, const Grid& grid, int perturb) {
+    LabSeedImage a;
     a.rgb = rgb;
     a.w = w;
     a.h = h;
@@ -262,9 +272,26 @@ hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pit
     a.cen = ws.cen;
     a.counts = ws.counts;
     a.sums = ws.sums;
+    a.tiles_x = (w + kTW - 1) / kTW;
+    return a;
+}
+
+hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
+                           int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
+                           hipStream_t s) {
+    const LabSeedImage a = lab_seed_image(rgb, w, h, pitch, channels, ws, grid, perturb);
+    const LabSeedTileMap none{nullptr, nullptr, nullptr};
     dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
     KernelTimer t("lab_seed", s);
-    lab_seed_kernel<<<g, kThreads, 0, s>>>(a, tab);
+    lab_seed_kernel<<<g, kThreads, 0, s>>>(a, none, tables());
+    return hipGetLastError();
+}
+
+hipError_t launch_lab_seed_batch(const LabSeedTileMap& map, int total_tiles, hipStream_t s) {
+    if (!map.images) return hipErrorInvalidValue;
+    LabSeedImage unused{};
+    KernelTimer t("lab_seed", s);
+    lab_seed_kernel<<<total_tiles, kThreads, 0, s>>>(unused, map, tables());
     return hipGetLastError();
 }
 

@@ -48,15 +48,62 @@ int scan_tiles_for(int n);
 // Launch wrappers (each returns the hipError_t of its launches).
 // CIELAB conversion of the image into ws.L/A/B fused with the seeding of
 // every centre (and the clearing of its count and first accumulators).
+struct LabSeedImage {
+    const uint8_t* rgb;
+    int w, h, pitch, channels;
+    float *L, *A, *B;
+    int S, ns_c, ns_r, perturb;
+    float* cen;
+    int32_t* counts;
+    long long* sums;  // first accumulator buffer
+    int tiles_x;      // conversion tiles per row
+};
+struct LabSeedTileMap {
+    const LabSeedImage* images;
+    const int* tile_image;
+    const int* tile_first;
+};
 hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
                            int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
                            hipStream_t s);
+hipError_t launch_lab_seed_batch(const LabSeedTileMap& map, int total_tiles, hipStream_t s);
+LabSeedImage lab_seed_image(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
+                            int32_t channels, const Workspace& ws, const Grid& grid, int perturb);
+int lab_seed_tile_w();
+int lab_seed_tile_h();
+// Per-image description of an association launch (constant across
+// launches; the launch number t selects the accumulator buffers).
+struct AssignImage {
+    const float* L;
+    const float* A;
+    const float* B;
+    int w, h, S, ns_c, ns_r, K;
+    float wgt;
+    float* cen;        // K x kCenStride: centres used by the last launch
+    int32_t* counts;   // K
+    int32_t* labels;   // N
+    long long* sums;   // ring of 3 x K x kSumStride accumulators
+    int tiles_x;       // workgroup tiles per row (for the launch's variant)
+};
+
+// Batch launches: workgroup b works on tile b - tile_first[i] of image
+// i = tile_image[b], described by images[i] (all in device memory).
+struct AssignTileMap {
+    const AssignImage* images;
+    const int* tile_image;
+    const int* tile_first;
+};
+
 // Association launch number t (0: the first, with the seeds as centres;
 // t >= 1 also completes the centre update of the previous launch).
 // variant: launch shape 1..assign_variant_count(); an unsupported value
 // falls back to assign_default_variant.
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
                          int variant, hipStream_t s);
+hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
+                               int variant, hipStream_t s);
+AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant);
+bool assign_tiles(int variant, int32_t w, int32_t h, int* tiles_x, int* tiles_y);
 int assign_variant_count();
 bool assign_variant_shape(int variant, int* vec, int* rows, int* tile_w, int* tile_h);
 bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S);
