@@ -15,7 +15,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "slic_oracle.c")]
+_SRCS = [os.path.join(_HERE, "slic_oracle.c"), os.path.join(_HERE, "net_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Flags that make the oracle's FP32 evaluation order the one written in the
@@ -68,6 +68,18 @@ def _load():
     lib.orc_weight.argtypes = [_F, _I]
     lib.orc_weight.restype = _F
     lib.orc_qshift.restype = ctypes.c_int
+    lib.orn_param_count.argtypes = [_I]
+    lib.orn_param_count.restype = ctypes.c_int
+    lib.orn_bf16.argtypes = [_D]
+    lib.orn_bf16.restype = _D
+    lib.orn_forward.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P]
+    lib.orn_forward.restype = ctypes.c_int
+    lib.orn_loss_grad.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P]
+    lib.orn_loss_grad.restype = ctypes.c_int
+    lib.orn_decode.argtypes = [_I, _I, _I, _P, _P]
+    lib.orn_decode.restype = ctypes.c_int
+    lib.orn_targets.argtypes = [_I, _I, _I, _P, _P]
+    lib.orn_targets.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -216,3 +228,80 @@ def segment(rgb: np.ndarray, S: int, m: float, iters: int, perturb: bool = True,
         seg, ns, sc = connectivity(labels, S, min_segment)
         res.update(seg_labels=seg, n_segments=ns, seg_cluster=sc)
     return res
+
+
+# ---------------------------------------------------------------------------
+# The learned warm start's net (see net_oracle.c).
+
+NET_C1, NET_C2, NET_C3 = 32, 32, 9
+
+
+def net_param_count(S: int) -> int:
+    return int(_load().orn_param_count(S))
+
+
+def net_offsets(S: int):
+    """Offsets of W1, b1, W2, b2, W3, b3, P in the flat parameter vector."""
+    w1 = 0
+    b1 = w1 + 9 * NET_C1 * 3
+    w2 = b1 + NET_C1
+    b2 = w2 + 9 * NET_C2 * NET_C1
+    w3 = b2 + NET_C2
+    b3 = w3 + 9 * NET_C3 * NET_C2
+    P = b3 + NET_C3
+    return {"W1": w1, "b1": b1, "W2": w2, "b2": b2, "W3": w3, "b3": b3, "P": P,
+            "end": P + S * S * NET_C3}
+
+
+def bf16(v: float) -> float:
+    return float(_load().orn_bf16(float(v)))
+
+
+def _lab3(lab):
+    return tuple(np.ascontiguousarray(v, np.float32) for v in lab)
+
+
+def net_forward(lab, params, S: int, bf16_mode: bool = True, origin=(0, 0)):
+    """Logits (H, W, 9) and the ReLU outputs a1, a2 (H, W, 32) of the net on
+    a region whose top-left pixel is `origin` = (x, y) in the full image."""
+    L, A, B = _lab3(lab)
+    h, w = L.shape
+    p = np.ascontiguousarray(params, np.float64)
+    assert p.size == net_param_count(S)
+    lg = np.empty((h, w, NET_C3), np.float64)
+    a1 = np.empty((h, w, NET_C1), np.float64)
+    a2 = np.empty((h, w, NET_C2), np.float64)
+    _check(_load().orn_forward(w, h, origin[0], origin[1], S, _ptr(L), _ptr(A), _ptr(B), _ptr(p),
+                               int(bf16_mode), _ptr(lg), _ptr(a1), _ptr(a2)), "net forward")
+    return lg, a1, a2
+
+
+def net_loss_grad(lab, params, S: int, target, bf16_mode: bool = True, origin=(0, 0),
+                  want_grad: bool = True):
+    """(mean cross-entropy, gradient or None)."""
+    L, A, B = _lab3(lab)
+    h, w = L.shape
+    p = np.ascontiguousarray(params, np.float64)
+    t = np.ascontiguousarray(target, np.int32)
+    loss = ctypes.c_double()
+    g = np.empty(p.size, np.float64) if want_grad else None
+    _check(_load().orn_loss_grad(w, h, origin[0], origin[1], S, _ptr(L), _ptr(A), _ptr(B), _ptr(t),
+                                 _ptr(p), int(bf16_mode), ctypes.byref(loss),
+                                 _ptr(g) if want_grad else None), "net loss")
+    return float(loss.value), g
+
+
+def net_decode(logits, S: int):
+    lg = np.ascontiguousarray(logits, np.float64)
+    h, w, _ = lg.shape
+    out = np.empty((h, w), np.int32)
+    _check(_load().orn_decode(w, h, S, _ptr(lg), _ptr(out)), "net decode")
+    return out
+
+
+def net_targets(labels, S: int):
+    lb = np.ascontiguousarray(labels, np.int32)
+    h, w = lb.shape
+    out = np.empty((h, w), np.int32)
+    _check(_load().orn_targets(w, h, S, _ptr(lb), _ptr(out)), "net targets")
+    return out

@@ -12,10 +12,12 @@ import oracle
 import test_oracle_assign as ta
 import test_oracle_ccl as tc
 import test_oracle_lab as tl
+import test_oracle_net as tn
 import test_oracle_seed as ts
 import test_oracle_update as tu
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "slic_oracle.c")
+NET_SRC = os.path.join(os.path.dirname(oracle.__file__), "net_oracle.c")
 
 # (name, original text, mutated text, pins expected to notice)
 MUTANTS = [
@@ -50,6 +52,21 @@ MUTANTS = [
      "*out = acc / ((double)w * (double)h + 1.0);", ["ccl"]),
 ]
 
+# mistakes planted in the warm-start net oracle
+NET_MUTANTS = [
+    ("net_tap_transposed", "                    int xx = x + t % 3 - 1, yy = y + t / 3 - 1;\n"
+     "                    if (xx < 0 || yy < 0 || xx >= n->w",
+     "                    int xx = x + t / 3 - 1, yy = y + t % 3 - 1;\n"
+     "                    if (xx < 0 || yy < 0 || xx >= n->w", ["net"]),
+    ("net_phase_axes", "int ph = ((y + n->oy) % n->S) * n->S + (x + n->ox) % n->S;",
+     "int ph = ((x + n->ox) % n->S) * n->S + (y + n->oy) % n->S;", ["net"]),
+    ("net_relu_mask", "if (!(n.a2[i] > 0.0)) d2[i] = 0.0;", "", ["net"]),
+    ("net_softmax_grad", "d[c] = (pr - (c == target[i] ? 1.0 : 0.0))",
+     "d[c] = (pr - (c == target[i] ? 0.5 : 0.0))", ["net"]),
+    ("net_input_scale", "n->x[3 * i + 1] = rnd(bf, (double)(A[i] / 128.0f));",
+     "n->x[3 * i + 1] = rnd(bf, (double)(A[i] / 100.0f));", ["net"]),
+]
+
 PINS = {
     "lab": [tl.test_white_is_exactly_100_0_0, tl.test_black, tl.test_published_colorimetry,
             tl.test_neutral_axis],
@@ -65,6 +82,8 @@ PINS = {
     "update": [lambda: [tu.test_update_is_the_exact_mean(s) for s in range(6)],
                tu.test_zero_iterations_is_one_association_with_the_seeds,
                lambda: tu.test_uniform_image_centres_land_on_cell_middles(15, 9, 3)],
+    "net": [lambda: [tn.test_backward_matches_central_differences(s) for s in range(2)],
+            lambda: [tn.test_forward_matches_scipy_correlation(s) for s in range(2)]],
     "ccl": [lambda: [tc.test_matches_independent_statement(s) for s in range(40)],
             lambda: [tc.test_invariants(s) for s in range(5)],
             lambda: [tc.test_energy_is_the_mean_eq1_distance(s) for s in range(3)]],
@@ -91,16 +110,21 @@ sys.exit(3 if tm._caught(pins) else 0)
 """
 
 
-@pytest.mark.parametrize("name,orig,mut,groups", MUTANTS, ids=[m[0] for m in MUTANTS])
+@pytest.mark.parametrize("name,orig,mut,groups", MUTANTS + NET_MUTANTS,
+                         ids=[m[0] for m in MUTANTS + NET_MUTANTS])
 def test_pins_reject_mutant(tmp_path, name, orig, mut, groups):
     """Each mutant runs in a child process, so one that crashes (an index
     gone out of range) counts as rejected without taking pytest down."""
-    src = open(SRC).read()
+    target = NET_SRC if groups == ["net"] else SRC
+    src = open(target).read()
     assert src.count(orig) == 1, f"mutation site for {name} not unique"
     path = tmp_path / "mutant.c"
     path.write_text(src.replace(orig, mut))
+    other = tmp_path / "other.c"
+    other.write_text(open(SRC if target == NET_SRC else NET_SRC).read())
     lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", *oracle.CFLAGS, str(path), "-o", str(lib), "-lm"], check=True)
+    subprocess.run(["gcc", *oracle.CFLAGS, str(path), str(other), "-o", str(lib), "-lm"],
+                   check=True)
     tests = os.path.dirname(os.path.abspath(__file__))
     code = _RUNNER.format(root=os.path.dirname(tests), tests=tests, lib=str(lib), groups=groups)
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=300)
