@@ -52,6 +52,8 @@ def _load():
         "orc_assign": [_P, _P, _P, _I, _I, _I, _F, _P, _P],
         "orc_update": [_P, _P, _P, _I, _I, _P, _I, _P, _P],
         "orc_kmeans": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _P, _P, _P],
+        "orc_kmeans_converge": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _F, _P, _P, _P, _P],
+        "orc_residual": [_P, _P, _I],
         "orc_energy": [_P, _P, _P, _I, _I, _I, _F, _P, _I, _P, _P],
         "orc_connectivity": [_P, _I, _I, _I, _I, _P, _P, _P],
         "orc_lab_tables": [_P, _P],
@@ -68,6 +70,7 @@ def _load():
     lib.orc_weight.argtypes = [_F, _I]
     lib.orc_weight.restype = _F
     lib.orc_qshift.restype = ctypes.c_int
+    lib.orc_residual.restype = ctypes.c_int64
     lib.orn_param_count.argtypes = [_I]
     lib.orn_param_count.restype = ctypes.c_int
     lib.orn_bf16.argtypes = [_D]
@@ -188,6 +191,30 @@ def kmeans(lab, S: int, m: float, perturb: bool, iters: int):
     _check(_load().orc_kmeans(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(perturb), iters,
                               _ptr(cen), _ptr(cnt), _ptr(lb)), "kmeans")
     return lb, cen, cnt
+
+
+def kmeans_converge(lab, S: int, m: float, perturb: bool, max_iters: int, threshold: float):
+    """Section 2's stopping rule: iterate until the summed L1 shift of the
+    centres (exact in units of 2^-18) is below threshold * K, at most
+    max_iters times.  Returns (labels, centres, counts, iterations run)."""
+    L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
+    h, w = L.shape
+    _, nc, nr = grid(w, h, S)
+    cen = np.empty((nc * nr, 5), np.float32)
+    cnt = np.empty(nc * nr, np.int32)
+    lb = np.empty((h, w), np.int32)
+    done = ctypes.c_int32()
+    _check(_load().orc_kmeans_converge(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(perturb),
+                                       max_iters, float(threshold), _ptr(cen), _ptr(cnt), _ptr(lb),
+                                       ctypes.byref(done)), "kmeans_converge")
+    return lb, cen, cnt, int(done.value)
+
+
+def residual(prev: np.ndarray, nxt: np.ndarray) -> int:
+    """Summed L1 distance between two centre sets, in units of 2^-18."""
+    a = np.ascontiguousarray(prev, np.float32)
+    b = np.ascontiguousarray(nxt, np.float32)
+    return int(_load().orc_residual(_ptr(a), _ptr(b), a.shape[0]))
 
 
 def energy(lab, S: int, m: float, centres: np.ndarray, labels: np.ndarray) -> float:

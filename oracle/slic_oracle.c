@@ -376,6 +376,48 @@ int orc_kmeans(const float* L, const float* A, const float* B, int32_t w, int32_
 }
 
 /* ------------------------------------------------------------------------
+ * Convergence stop (Section 2: the loop ends once the L1 distance between
+ * the centres of consecutive iterations falls below a threshold).
+ * READING: the distance is summed over every centre and its five components
+ * (L, a, b, x, y), each |difference| taken in FP64 and quantised to
+ * rint(|d| * 2^18) so that the sum is an exact integer; the threshold T is
+ * the mean shift per centre, so the loop stops after the first iteration i
+ * (update, then association) whose sum is below rint(T * 2^18) * K.  At most
+ * max_iters iterations; *iters_done receives the number run.
+ * ---------------------------------------------------------------------- */
+int64_t orc_residual(const float* prev, const float* next, int32_t K) {
+    int64_t r = 0;
+    for (size_t i = 0; i < (size_t)K * 5; i++)
+        r += llrint(fabs((double)next[i] - (double)prev[i]) * (double)(1 << ORC_QSHIFT));
+    return r;
+}
+
+int orc_kmeans_converge(const float* L, const float* A, const float* B, int32_t w, int32_t h,
+                        int32_t S, float m, int32_t perturb, int32_t max_iters, float threshold,
+                        float* centres, int32_t* counts, int32_t* labels, int32_t* iters_done) {
+    if (w < 1 || h < 1 || S < 1 || max_iters < 0 || !iters_done || !(threshold >= 0.0f))
+        return ORC_EINVAL;
+    int32_t K = ((w + S - 1) / S) * ((h + S - 1) / S);
+    const int64_t limit = llrint((double)threshold * (double)(1 << ORC_QSHIFT)) * (int64_t)K;
+    float* prev = malloc(sizeof(float) * 5 * (size_t)K);
+    if (!prev) return ORC_ENOMEM;
+    int rc = orc_seed(L, A, B, w, h, S, perturb, centres);
+    for (int32_t k = 0; !rc && k < K; k++) counts[k] = 0;
+    if (!rc) rc = orc_assign(L, A, B, w, h, S, m, centres, labels);
+    *iters_done = 0;
+    for (int32_t it = 0; !rc && it < max_iters; it++) {
+        memcpy(prev, centres, sizeof(float) * 5 * (size_t)K);
+        rc = orc_update(L, A, B, w, h, labels, K, centres, counts);
+        if (!rc) rc = orc_assign(L, A, B, w, h, S, m, centres, labels);
+        if (rc) break;
+        *iters_done = it + 1;
+        if (orc_residual(prev, centres, K) < limit) break;
+    }
+    free(prev);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
  * O7. Energy: the mean over pixels of Eq. 1's D_s between each pixel and the
  * centre it is associated with, each term computed exactly as in O3 and
  * summed in FP64 in raster order.
