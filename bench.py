@@ -201,6 +201,107 @@ def bench_c4(slic, torch, dev, reps: int):
             "assign_hbm_frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
+def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps: int,
+             hd: bool = False):
+    """Workload c5: the learned warm start.  Trains the net on the GPU (crops
+    of c5 training images, targets from plain 10-iteration SLIC), then on
+    ``n_eval`` evaluation images compares plain SLIC (convert + seed + 10
+    iterations) with the warm start (convert + net + 2 iterations + energy):
+    frames/s of each, the per-image energy ratio, the gate's pass rate
+    (E_warm <= 1.01 E_plain), frames/s with failing images charged warm +
+    plain time, and label agreement with plain SLIC."""
+    import numpy as np
+
+    import synth
+    from synth.configs import warm_eval_workload, warm_train_workload
+    S, warm_iters, plain_iters = 16, 2, 10
+    t0 = time.perf_counter()
+    train = []
+    for j in range(n_train):
+        w = warm_train_workload(j)
+        train.append((torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev),
+                      slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb)))
+    data = slic.warm.TrainingSet(train, plain_iters)
+    net = slic.warm.Net(S, 32, 128, 128, seed=1)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    log = slic.warm.train(net, data, train_steps, seed=2, log_every=max(1, train_steps // 4))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    evals = [warm_eval_workload(j, hd) for j in range(n_eval)]
+    imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in evals]
+    params = [slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb) for w in evals]
+    cps = [p.c() for p in params]
+    stream = torch.cuda.current_stream().cuda_stream
+    ws_plain = torch.empty(slic.slic_workspace_bytes(cps[0]), dtype=torch.uint8, device=dev)
+    ws_warm = torch.empty(slic.slic_warm_workspace_bytes(cps[0]), dtype=torch.uint8, device=dev)
+    lab_plain = [torch.empty((w.height, w.width), dtype=torch.int32, device=dev) for w in evals]
+    lab_warm = [torch.empty((w.height, w.width), dtype=torch.int32, device=dev) for w in evals]
+    e_plain = torch.empty(n_eval, dtype=torch.float64, device=dev)
+    e_warm = torch.empty(n_eval, dtype=torch.float64, device=dev)
+    slic.slic_autotune(cps[0], imgs[0].data_ptr(), plain_iters, 3, stream, ws_plain.data_ptr(),
+                       ws_plain.numel())
+
+    def run_plain(with_energy):
+        for i in range(n_eval):
+            slic.slic_segment(cps[i], imgs[i].data_ptr(), plain_iters, 0, lab_plain[i].data_ptr(),
+                              None, e_plain[i:].data_ptr() if with_energy else None, None, stream,
+                              ws_plain.data_ptr(), ws_plain.numel())
+
+    def run_warm():
+        for i in range(n_eval):
+            slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), net.params.data_ptr(), warm_iters,
+                                   0, lab_warm[i].data_ptr(), None, e_warm[i:].data_ptr(), None,
+                                   stream, ws_warm.data_ptr(), ws_warm.numel())
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t)
+        runs.sort()
+        return runs[len(runs) // 2]
+
+    t_plain = timed(lambda: run_plain(False))
+    t_warm = timed(run_warm)
+    run_plain(True)
+    run_warm()
+    torch.cuda.synchronize()
+    ep, ew = e_plain.cpu().numpy(), e_warm.cpu().numpy()
+    ratio = ew / ep
+    passed = ratio <= 1.01
+    agree = [float((a == b).float().mean()) for a, b in zip(lab_warm, lab_plain)]
+    # plain energies at the warm start's iteration count, for the gain
+    e2 = torch.empty(n_eval, dtype=torch.float64, device=dev)
+    for i in range(n_eval):
+        slic.slic_segment(cps[i], imgs[i].data_ptr(), warm_iters, 0, lab_plain[i].data_ptr(), None,
+                          e2[i:].data_ptr(), None, stream, ws_plain.data_ptr(), ws_plain.numel())
+    e2 = e2.cpu().numpy()
+    t_charged = t_warm + t_plain * float((~passed).sum()) / n_eval
+    w0 = evals[0]
+    return {"images": n_eval, "size": f"{w0.width}x{w0.height}", "S": S,
+            "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
+                      "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                      "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
+                      "loss": [[s, round(v, 4)] for s, v in log]},
+            "plain_iters": plain_iters, "warm_iters": warm_iters,
+            "plain_frames_per_s": round(n_eval / t_plain, 1),
+            "warm_frames_per_s": round(n_eval / t_warm, 1),
+            "warm_frames_per_s_fallback_charged": round(n_eval / t_charged, 1),
+            "gate_pass_rate": round(float(passed.mean()), 4),
+            "energy_ratio_mean": round(float(ratio.mean()), 4),
+            "energy_ratio_max": round(float(ratio.max()), 4),
+            "plain_2iter_energy_ratio_mean": round(float((e2 / ep).mean()), 4),
+            "warm_below_plain_2iter": int((ew < e2).sum()),
+            "label_agreement_mean": round(float(np.mean(agree)), 4)}
+
+
 def traffic_from_profile():
     """HBM bytes per association launch from the committed PMC summary, or
     None if it is missing or the kernel source changed since."""
@@ -242,6 +343,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=600,
+                    help="Adam steps of the warm-start net in the c5 leg")
+    ap.add_argument("--train-images", type=int, default=64,
+                    help="c5 training images for the warm-start net")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (PMC calibration)")
     ap.add_argument("--workload-only", default=None, metavar="NAME",
@@ -320,6 +425,8 @@ def main() -> int:
                 entry["assign_hbm_frac"] = round(b / (a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             extra[name] = entry
         extra["c4"] = bench_c4(slic, torch, dev, reps=max(5, args.steps // 50))
+        extra["c5"] = bench_c5(slic, torch, dev, args.train_steps, args.train_images, 32,
+                               reps=max(3, args.steps // 100))
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

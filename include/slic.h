@@ -91,13 +91,26 @@ int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* 
  * slic_iterate(c, a + b).  SLIC_ESTATE after slic_enforce_connectivity. */
 int slic_iterate(slic_ctx* ctx, int32_t n_iters);
 
+/* Section 2's stopping rule: rounds of (update, associate) until the L1
+ * distance between the centres before and after an update, summed over all
+ * centres and their five components (L, a, b, x, y) with each |difference|
+ * rounded to a multiple of 2^-18, is below threshold * K (threshold: the
+ * mean shift per centre, >= 0), at most max_iters rounds.  The round that
+ * meets the rule still associates.  The decision is taken on the device
+ * (later launches exit at once), so nothing synchronises the host;
+ * *d_iters_done (device int32, may be NULL) receives the rounds run.
+ * Afterwards the context is final: slic_iterate returns SLIC_ESTATE, the
+ * energy, copies and connectivity remain available. */
+int slic_iterate_converge(slic_ctx* ctx, int32_t max_iters, float threshold,
+                          int32_t* d_iters_done);
+
 /* Connectivity clean-up (Section 2, last step): relabels the context's
  * label map in place into 4-connected segments, merging every segment below
  * the size threshold (slic_params.min_segment) into the segment left of
  * (or, at a row start, above) its first pixel; segments are numbered 0..
  * in raster order of their first pixel.  *d_n_segments (device int32, may
- * be NULL) receives their count.  Afterwards slic_iterate returns
- * SLIC_ESTATE; the centres stay those of the last association. */
+ * be NULL) receives their count.  Afterwards slic_iterate and slic_energy
+ * return SLIC_ESTATE; the centres stay those of the last association. */
 int slic_enforce_connectivity(slic_ctx* ctx, int32_t* d_n_segments);
 
 /* Copies of the context's state (device to device, on the context's
@@ -182,6 +195,98 @@ void slic_batch_destroy(slic_batch* b);
 int slic_segment_batch(const slic_params* per_image, const uint8_t* const* d_rgb, int32_t n_images,
                        int32_t n_iters, int32_t enforce, int32_t* const* d_labels,
                        int32_t* d_n_segments, void* hip_stream, void* d_ws, size_t ws_bytes);
+
+/* Learned warm start (an extension beyond the paper, whose Section 4 loop
+ * starts every frame from grid seeds).  A small convolutional net predicts,
+ * per pixel, which of the nine grid cells around the pixel's own cell holds
+ * the centre the pixel is associated with after plain SLIC; the decoded
+ * label map replaces the first association, so fewer (update, associate)
+ * rounds reach the same energy.
+ *
+ * The net: input (L/100, a/128, b/128) of the CIELAB image; 3x3 convolution
+ * 3 -> 32, ReLU, 3x3 convolution 32 -> 32, ReLU, 3x3 convolution 32 -> 9,
+ * plus a learned bias per grid phase P[(y mod S) * S + (x mod S)][9] added to
+ * the nine logits.  Zero padding at the borders of the region it runs on.
+ * Inputs, weights and activations are rounded to bfloat16 (nearest even),
+ * accumulation is FP32 (matrix cores); biases and P stay FP32.
+ * Parameters: one device float vector of slic_net_param_count(S) values,
+ *   W1[9][32][3], b1[32], W2[9][32][32], b2[32], W3[9][9][32], b3[9],
+ *   P[S*S][9],
+ * with W[tap][out][in], tap = (dy + 1) * 3 + (dx + 1) weighting the input at
+ * (x + dx, y + dy).  Class c of the logits names the cell (cy + c / 3 - 1,
+ * cx + c % 3 - 1) around the pixel's cell (cx, cy) = (x / S, y / S),
+ * clamped into the grid.
+ *
+ * Training works on batches of crops: crop i is the crop_w x crop_h region
+ * of an image whose top-left pixel is (ox, oy); pixels beyond the image's
+ * right or bottom edge are zero inputs and carry no target.  Grid phases are
+ * those of the full image. */
+typedef struct {
+    const float* d_L;         /* planar CIELAB of the image, float[img_h * img_w] each */
+    const float* d_a;
+    const float* d_b;
+    const int32_t* d_labels;  /* the image's converged labels (slic_net_targets only), else NULL */
+    int32_t img_w, img_h;     /* image size */
+    int32_t ox, oy;           /* crop origin, 0 <= ox < img_w, 0 <= oy < img_h */
+} slic_net_crop;
+
+/* Number of parameters for grid step S (1 <= S <= 32; 0 otherwise). */
+int32_t slic_net_param_count(int32_t S);
+
+/* Device workspace of the net calls below for n_crops (1..32) crops of
+ * crop_w x crop_h pixels at grid step S (about 330 bytes per pixel); 0 if the
+ * shape is invalid. */
+size_t slic_net_workspace_bytes(int32_t n_crops, int32_t crop_w, int32_t crop_h, int32_t S);
+
+/* Forward pass: writes d_logits float[n_crops][crop_h][crop_w][9]. */
+int slic_net_forward(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                     int32_t S, const float* d_params, float* d_logits, void* hip_stream,
+                     void* d_ws, size_t ws_bytes);
+
+/* Mean softmax cross-entropy over the pixels whose target (int32[n_crops]
+ * [crop_h][crop_w], class 0..8, or -1: no target) is a class, and its
+ * gradient with respect to every parameter (d_grad: float[param_count],
+ * overwritten; the rounded weights' gradients are passed straight through).
+ * *d_loss (device double, may be NULL) receives the loss.  Deterministic:
+ * partial sums per workgroup are added in a fixed order. */
+int slic_net_loss_grad(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                       int32_t S, const float* d_params, const int32_t* d_target, float* d_grad,
+                       double* d_loss, void* hip_stream, void* d_ws, size_t ws_bytes);
+
+/* Training targets from each crop's d_labels (grid-indexed cluster labels):
+ * the class (dy + 1) * 3 + (dx + 1) of the label's cell (cx + dx, cy + dy)
+ * relative to the pixel's cell, -1 if it is not one of the nine or the
+ * pixel lies outside the image.  d_target: int32[n_crops][crop_h][crop_w]. */
+int slic_net_targets(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                     int32_t S, int32_t* d_target, void* hip_stream);
+
+/* One Adam step (Kingma and Ba) on count parameters: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step))
+ * + eps); step >= 1 counts from 1.  d_m and d_v start at zero. */
+int slic_net_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t count,
+                  int32_t step, float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+/* Warm-started segmentation.  slic_warm_init converts d_rgb, seeds the
+ * centres exactly as slic_init does, runs the net on the whole image and
+ * takes its decoded label map as the first association (in place of
+ * slic_init's association with the seeds).  The context then behaves as one
+ * from slic_init: slic_iterate(ctx, n) runs n rounds of (update, associate),
+ * the first update using the net's labels; a cluster that no pixel chose
+ * keeps its seed.  d_net_params: slic_net_param_count(S) floats for the
+ * step S of p.  Workspace: slic_warm_workspace_bytes(p) bytes (the
+ * segmentation's plus the net's forward buffers, about 256 bytes per pixel).
+ * slic_warm_segment runs init, n_iters rounds, the energy (d_energy may be
+ * NULL) and, with enforce, connectivity, like slic_segment.
+ * Gate: the warm result is meant to replace plain SLIC only where its energy
+ * is at most 1.01 times plain SLIC's; that comparison is the caller's (it
+ * needs the plain energy). */
+size_t slic_warm_workspace_bytes(const slic_params* p);
+int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                   const float* d_net_params, void* hip_stream, void* d_ws, size_t ws_bytes);
+int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
+                      int32_t n_iters, int32_t enforce, int32_t* d_labels, float* d_centres,
+                      double* d_energy, int32_t* d_n_segments, void* hip_stream, void* d_ws,
+                      size_t ws_bytes);
 
 /* Kernel timing for measurement.  slic_timing_enable(1) forgets earlier
  * records and starts recording: every kernel launch of the library is then

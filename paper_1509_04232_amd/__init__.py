@@ -18,11 +18,16 @@ from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, S
                    slic_destroy, slic_segment_batch,
                    slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
                    slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
-                   slic_iterate, slic_segment, slic_set_assign_variant, slic_strerror,
-                   slic_timing_enable, slic_timing_read, slic_workspace_bytes)
+                   slic_iterate, slic_iterate_converge, slic_segment, slic_set_assign_variant,
+                   slic_strerror,
+                   slic_timing_enable, slic_timing_read, slic_workspace_bytes,
+                   SlicNetCrop, slic_net_adam, slic_net_forward, slic_net_loss_grad,
+                   slic_net_param_count, slic_net_targets, slic_net_workspace_bytes,
+                   slic_warm_init, slic_warm_segment, slic_warm_workspace_bytes)
 
 __all__ = [
     "Params", "Context", "Batch", "segment", "workspace_for", "SlicError", "SlicParams",
+    "SlicNetCrop", "warm",
     *EXPORTED,
 ]
 
@@ -74,22 +79,37 @@ def workspace_for(p: Params, device=None) -> torch.Tensor:
 
 
 class Context:
-    """A slic_ctx: slic_init on construction, then iterate / enforce / get."""
+    """A slic_ctx: slic_init on construction (slic_warm_init when the net's
+    parameters are given), then iterate / enforce / get."""
 
-    def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None):
+    def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None,
+                 net_params: torch.Tensor | None = None):
         _check_rgb(rgb, p)
         self.params = p
         self._cp = p.c()
         self.stream = stream
-        self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
         self._rgb = rgb  # kept alive until the conversion has run
-        self.ctx = slic_init(self._cp, rgb.data_ptr(), _stream(stream), self.ws.data_ptr(),
-                             self.ws.numel())
+        if net_params is None:
+            self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
+            self.ctx = slic_init(self._cp, rgb.data_ptr(), _stream(stream), self.ws.data_ptr(),
+                                 self.ws.numel())
+        else:
+            self.ws = workspace if workspace is not None else torch.empty(
+                slic_warm_workspace_bytes(self._cp), dtype=torch.uint8, device=rgb.device)
+            self._net = net_params
+            self.ctx = slic_warm_init(self._cp, rgb.data_ptr(), net_params.data_ptr(),
+                                      _stream(stream), self.ws.data_ptr(), self.ws.numel())
         self.device = rgb.device
 
     def iterate(self, n: int) -> "Context":
         slic_iterate(self.ctx, n)
         return self
+
+    def iterate_converge(self, max_iters: int, threshold: float) -> torch.Tensor:
+        """Section 2's stopping rule; returns the rounds run (device int32)."""
+        n = torch.empty(1, dtype=torch.int32, device=self.device)
+        slic_iterate_converge(self.ctx, max_iters, threshold, n.data_ptr())
+        return n
 
     def enforce_connectivity(self) -> torch.Tensor:
         n = torch.empty(1, dtype=torch.int32, device=self.device)
@@ -191,3 +211,6 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+from . import warm  # noqa: E402  (uses Params and _check_rgb above)

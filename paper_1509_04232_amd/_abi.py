@@ -30,6 +30,14 @@ class SlicParams(ctypes.Structure):
     ]
 
 
+class SlicNetCrop(ctypes.Structure):
+    _fields_ = [
+        ("d_L", ctypes.c_void_p), ("d_a", ctypes.c_void_p), ("d_b", ctypes.c_void_p),
+        ("d_labels", ctypes.c_void_p), ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32),
+        ("ox", ctypes.c_int32), ("oy", ctypes.c_int32),
+    ]
+
+
 class SlicError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -39,12 +47,14 @@ class SlicError(RuntimeError):
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _PP = ctypes.POINTER(SlicParams)
+_CP = ctypes.POINTER(SlicNetCrop)
 
 _SIGS = {
     "slic_workspace_bytes": ([_PP], ctypes.c_size_t),
     "slic_grid": ([_PP, _P, _P, _P], ctypes.c_int),
     "slic_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_iterate": ([_P, _I], ctypes.c_int),
+    "slic_iterate_converge": ([_P, _I, ctypes.c_float, _P], ctypes.c_int),
     "slic_enforce_connectivity": ([_P, _P], ctypes.c_int),
     "slic_get_labels": ([_P, _P], ctypes.c_int),
     "slic_get_centres": ([_P, _P, _P], ctypes.c_int),
@@ -65,6 +75,18 @@ _SIGS = {
     "slic_batch_autotune": ([_P, _P, _I, _P, _P], ctypes.c_int),
     "slic_batch_destroy": ([_P], None),
     "slic_segment_batch": ([_PP, _P, _I, _I, _I, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_net_param_count": ([_I], ctypes.c_int32),
+    "slic_net_workspace_bytes": ([_I, _I, _I, _I], ctypes.c_size_t),
+    "slic_net_forward": ([_CP, _I, _I, _I, _I, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_net_loss_grad": ([_CP, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t],
+                           ctypes.c_int),
+    "slic_net_targets": ([_CP, _I, _I, _I, _I, _P, _P], ctypes.c_int),
+    "slic_net_adam": ([_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                       ctypes.c_float, _P], ctypes.c_int),
+    "slic_warm_workspace_bytes": ([_PP], ctypes.c_size_t),
+    "slic_warm_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_warm_segment": ([_PP, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t],
+                          ctypes.c_int),
     "slic_timing_enable": ([_I], ctypes.c_int),
     "slic_timing_read": ([ctypes.c_char_p, _P, _P], ctypes.c_int),
 }
@@ -103,6 +125,12 @@ def slic_init(p: SlicParams, d_rgb: int, stream: int, d_ws: int, ws_bytes: int) 
 
 def slic_iterate(ctx: int, n_iters: int) -> None:
     _check(lib.slic_iterate(ctx, n_iters), "slic_iterate")
+
+
+def slic_iterate_converge(ctx: int, max_iters: int, threshold: float,
+                          d_iters_done: int | None) -> None:
+    _check(lib.slic_iterate_converge(ctx, max_iters, threshold, d_iters_done),
+           "slic_iterate_converge")
 
 
 def slic_enforce_connectivity(ctx: int, d_n_segments: int | None) -> None:
@@ -234,3 +262,68 @@ def slic_timing_read(prefix: str | None = None):
     _check(lib.slic_timing_read(prefix.encode() if prefix else None, ctypes.byref(ms),
                                 ctypes.byref(n)), "slic_timing_read")
     return float(ms.value), int(n.value)
+
+
+def _crops(crops):
+    return (SlicNetCrop * len(crops))(*crops)
+
+
+def slic_net_param_count(S: int) -> int:
+    n = int(lib.slic_net_param_count(S))
+    if n == 0:
+        raise SlicError(SLIC_EINVAL, "slic_net_param_count")
+    return n
+
+
+def slic_net_workspace_bytes(n_crops: int, crop_w: int, crop_h: int, S: int) -> int:
+    n = lib.slic_net_workspace_bytes(n_crops, crop_w, crop_h, S)
+    if n == 0:
+        raise SlicError(SLIC_EINVAL, "slic_net_workspace_bytes")
+    return int(n)
+
+
+def slic_net_forward(crops, crop_w: int, crop_h: int, S: int, d_params: int, d_logits: int,
+                     stream: int, d_ws: int, ws_bytes: int) -> None:
+    _check(lib.slic_net_forward(_crops(crops), len(crops), crop_w, crop_h, S, d_params, d_logits,
+                                stream, d_ws, ws_bytes), "slic_net_forward")
+
+
+def slic_net_loss_grad(crops, crop_w: int, crop_h: int, S: int, d_params: int, d_target: int,
+                       d_grad: int, d_loss: int | None, stream: int, d_ws: int,
+                       ws_bytes: int) -> None:
+    _check(lib.slic_net_loss_grad(_crops(crops), len(crops), crop_w, crop_h, S, d_params, d_target,
+                                  d_grad, d_loss, stream, d_ws, ws_bytes), "slic_net_loss_grad")
+
+
+def slic_net_targets(crops, crop_w: int, crop_h: int, S: int, d_target: int, stream: int) -> None:
+    _check(lib.slic_net_targets(_crops(crops), len(crops), crop_w, crop_h, S, d_target, stream),
+           "slic_net_targets")
+
+
+def slic_net_adam(d_params: int, d_grad: int, d_m: int, d_v: int, count: int, step: int,
+                  lr: float, beta1: float, beta2: float, eps: float, stream: int) -> None:
+    _check(lib.slic_net_adam(d_params, d_grad, d_m, d_v, count, step, lr, beta1, beta2, eps,
+                             stream), "slic_net_adam")
+
+
+def slic_warm_workspace_bytes(p: SlicParams) -> int:
+    n = lib.slic_warm_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise SlicError(SLIC_EINVAL, "slic_warm_workspace_bytes")
+    return int(n)
+
+
+def slic_warm_init(p: SlicParams, d_rgb: int, d_net_params: int, stream: int, d_ws: int,
+                   ws_bytes: int) -> int:
+    ctx = _P()
+    _check(lib.slic_warm_init(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_net_params, stream,
+                              d_ws, ws_bytes), "slic_warm_init")
+    return int(ctx.value)
+
+
+def slic_warm_segment(p: SlicParams, d_rgb: int, d_net_params: int, n_iters: int, enforce: int,
+                      d_labels: int, d_centres: int | None, d_energy: int | None,
+                      d_n_segments: int | None, stream: int, d_ws: int, ws_bytes: int) -> None:
+    _check(lib.slic_warm_segment(ctypes.byref(p), d_rgb, d_net_params, n_iters, enforce, d_labels,
+                                 d_centres, d_energy, d_n_segments, stream, d_ws, ws_bytes),
+           "slic_warm_segment")

@@ -90,6 +90,7 @@ size_t workspace_layout(int32_t width, int32_t height, const Grid& g, Workspace*
     w.ccl3 = reinterpret_cast<int32_t*>(take(n * sizeof(int32_t)));
     w.scan = reinterpret_cast<int32_t*>(take(static_cast<size_t>(nscan) * sizeof(int32_t)));
     w.partial = reinterpret_cast<double*>(take(static_cast<size_t>(nenergy) * sizeof(double)));
+    w.ctl = reinterpret_cast<long long*>(take(8 * sizeof(long long)));
     w.n_scan_blocks = nscan;
     w.n_energy_blocks = nenergy;
     if (ws) *ws = w;
@@ -434,9 +435,32 @@ int slic_iterate(slic_ctx* c, int32_t n_iters) {
     return enqueue_iterations(c, n_iters) == hipSuccess ? SLIC_OK : fail(c);
 }
 
+int slic_iterate_converge(slic_ctx* c, int32_t max_iters, float threshold,
+                          int32_t* d_iters_done) {
+    if (!c || max_iters < 0 || !(threshold >= 0.0f) || !std::isfinite(threshold))
+        return SLIC_EINVAL;
+    if (d_iters_done && check_device_ptr(d_iters_done) != SLIC_OK) return SLIC_EINVAL;
+    if (c->state != 0) return SLIC_ESTATE;
+    const double q = std::ldexp(static_cast<double>(threshold), kQShift);
+    if (q * static_cast<double>(c->g.K) > 4.0e18) return SLIC_EINVAL;
+    const Converge cv{c->ws.ctl, std::llrint(q) * static_cast<long long>(c->g.K), c->t};
+    if (launch_converge_reset(c->ws.ctl, c->stream) != hipSuccess) return fail(c);
+    for (int32_t i = 0; i < max_iters; ++i) {
+        if (launch_assign(c->ws, c->p.width, c->p.height, c->g, c->t, c->variant, c->stream, &cv) !=
+            hipSuccess)
+            return fail(c);
+        ++c->t;
+    }
+    if (d_iters_done && launch_converge_result(c->ws.ctl, max_iters, d_iters_done, c->stream) !=
+                            hipSuccess)
+        return fail(c);
+    c->state = 3;
+    return SLIC_OK;
+}
+
 int slic_enforce_connectivity(slic_ctx* c, int32_t* d_n_segments) {
     if (!c) return SLIC_EINVAL;
-    if (c->state != 0) return SLIC_ESTATE;
+    if (c->state != 0 && c->state != 3) return SLIC_ESTATE;
     if (launch_connectivity(c->ws, c->p.width, c->p.height, c->g, c->p.min_segment, c->ws.labels,
                             d_n_segments, c->stream) != hipSuccess)
         return fail(c);
@@ -476,7 +500,7 @@ int slic_get_lab(const slic_ctx* c, float* d_L, float* d_a, float* d_b) {
 
 int slic_energy(const slic_ctx* c, double* d_out) {
     if (!c || !d_out) return SLIC_EINVAL;
-    if (c->state != 0) return SLIC_ESTATE;
+    if (c->state != 0 && c->state != 3) return SLIC_ESTATE;
     if (launch_energy(c->ws, c->p.width, c->p.height, c->g, d_out, c->stream) != hipSuccess)
         return fail(const_cast<slic_ctx*>(c));
     return SLIC_OK;
@@ -495,6 +519,95 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
     bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;  // associate straight into the caller's buffer
     if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
+    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
+    if (d_energy &&
+        launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
+                                       d_n_segments, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    return SLIC_OK;
+}
+
+namespace {
+
+// Byte offset of the net's buffers in a warm-start workspace (after the
+// segmentation's own), or 0 if the parameters do not support the net.
+size_t warm_split(const slic_params* p, Grid* g) {
+    if (!params_ok(p)) return 0;
+    compute_grid(p, g);
+    if (warm_net_bytes(p->width, p->height, g->S) == 0) return 0;
+    return align_up(workspace_layout(p->width, p->height, *g, nullptr, nullptr));
+}
+
+// slic_init with the net's decoded labels as the first association.
+hipError_t enqueue_warm_init(slic_ctx* c, const uint8_t* rgb, const float* net_params,
+                             void* net_ws) {
+    const slic_params& p = c->p;
+    hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
+                                   (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
+    if (e != hipSuccess) return e;
+    c->t = 0;
+    e = launch_warm_start(c->ws, p.width, p.height, c->g, net_params, net_ws, c->stream);
+    if (e == hipSuccess) c->t = 1;
+    return e;
+}
+
+int check_warm_args(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
+                    void* d_ws, size_t ws_bytes, size_t* split) {
+    Grid g;
+    *split = warm_split(p, &g);
+    if (*split == 0 || !d_rgb || !d_net_params || !d_ws || !aligned(d_ws)) return SLIC_EINVAL;
+    if (ws_bytes < *split + warm_net_bytes(p->width, p->height, g.S)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc) return rc;
+    return check_device_ptr(d_net_params);
+}
+
+}  // namespace
+
+size_t slic_warm_workspace_bytes(const slic_params* p) {
+    Grid g;
+    const size_t split = warm_split(p, &g);
+    if (split == 0) return 0;
+    return split + warm_net_bytes(p->width, p->height, g.S);
+}
+
+int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                   const float* d_net_params, void* hip_stream, void* d_ws, size_t ws_bytes) {
+    if (!out) return SLIC_EINVAL;
+    *out = nullptr;
+    size_t split = 0;
+    int rc = check_warm_args(p, d_rgb, d_net_params, d_ws, ws_bytes, &split);
+    if (rc) return rc;
+    slic_ctx* c = new (std::nothrow) slic_ctx;
+    if (!c) return SLIC_ENOMEM;
+    bind(c, p, d_ws, hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        enqueue_warm_init(c, d_rgb, d_net_params, static_cast<char*>(d_ws) + split) != hipSuccess) {
+        delete c;
+        return SLIC_EHIP;
+    }
+    *out = c;
+    return SLIC_OK;
+}
+
+int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
+                      int32_t n_iters, int32_t enforce, int32_t* d_labels, float* d_centres,
+                      double* d_energy, int32_t* d_n_segments, void* hip_stream, void* d_ws,
+                      size_t ws_bytes) {
+    if (n_iters < 0 || !d_labels) return SLIC_EINVAL;
+    size_t split = 0;
+    int rc = check_warm_args(p, d_rgb, d_net_params, d_ws, ws_bytes, &split);
+    if (rc) return rc;
+    if ((rc = check_device_ptr(d_labels)) != 0) return rc;
+    slic_ctx c;
+    bind(&c, p, d_ws, hip_stream);
+    c.ws.labels = d_labels;
+    if (enqueue_warm_init(&c, d_rgb, d_net_params, static_cast<char*>(d_ws) + split) != hipSuccess)
+        return SLIC_EHIP;
     if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
         launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)

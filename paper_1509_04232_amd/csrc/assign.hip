@@ -141,9 +141,25 @@ __device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, in
 
 template <int VEC, int ROWS>
 __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, AssignTileMap map,
-                                                          long long t) {
+                                                          long long t, Converge cv) {
     using Sh = Shape<VEC, ROWS>;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long s_shift;
+    if (cv.ctl) {  // convergence stop: every workgroup takes the same decision
+        if (cv.ctl[3] != 0) return;
+        if (t > cv.t_first && cv.ctl[(t - 1) % 3] < cv.limit) {
+            if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+                cv.ctl[3] = 1;
+                cv.ctl[4] = t - cv.t_first;
+            }
+            return;
+        }
+        if (threadIdx.x == 0) {
+            s_shift = 0ull;
+            if (blockIdx.x == 0 && blockIdx.y == 0) cv.ctl[(t + 1) % 3] = 0;
+        }
+    }
+    long long my_shift = 0;
     AssignImage g;
     int bx, by;
     resolve_image(single, map, &g, &bx, &by);
@@ -225,6 +241,15 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
                                 static_cast<float>(static_cast<double>(s[3]) / dn));
                 vy = static_cast<float>(static_cast<double>(s[4]) / dn);
                 if (owner) {
+                    if (cv.ctl) {  // L1 shift, each component rint(|d| 2^18)
+                        const float4 o = *reinterpret_cast<const float4*>(c);
+                        const double q = static_cast<double>(1 << kQShift);
+                        my_shift += llrint(fabs(static_cast<double>(v.x) - o.x) * q) +
+                                    llrint(fabs(static_cast<double>(v.y) - o.y) * q) +
+                                    llrint(fabs(static_cast<double>(v.z) - o.z) * q) +
+                                    llrint(fabs(static_cast<double>(v.w) - o.w) * q) +
+                                    llrint(fabs(static_cast<double>(vy) - c[4]) * q);
+                    }
                     *reinterpret_cast<float4*>(c) = v;
                     c[4] = vy;
                 }
@@ -245,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         ceny[i] = vy;
     }
     __syncthreads();
+    if (my_shift) atomicAdd(&s_shift, static_cast<unsigned long long>(my_shift));
 
     // ---- associate: fast distances for every candidate, shared by the VEC
     // pixels of a row (they lie in one cell)
@@ -330,6 +356,8 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
     }
     if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
     __syncthreads();
+    if (cv.ctl && threadIdx.x == 0 && s_shift)
+        atomicAdd(reinterpret_cast<unsigned long long*>(cv.ctl + t % 3), s_shift);
 
     // ---- add the workgroup's bins to the global sums
     for (int i = threadIdx.x; i < ncells; i += kThreads) {
@@ -347,6 +375,14 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         atomicAdd(s + 4, static_cast<unsigned long long>(sy));
         atomicAdd(s + 5, static_cast<unsigned long long>(n));
     }
+}
+
+__global__ void converge_reset_kernel(long long* ctl) {
+    if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
+}
+
+__global__ void converge_result_kernel(const long long* ctl, int max_iters, int32_t* out) {
+    if (threadIdx.x == 0) *out = ctl[3] ? static_cast<int32_t>(ctl[4]) : max_iters;
 }
 
 constexpr int kEnergyBlock = 256;
@@ -408,7 +444,7 @@ size_t variant_lds(int S) {
 
 template <int VEC, int ROWS>
 hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int total_tiles,
-                          int min_S, long long t, hipStream_t s) {
+                          int min_S, long long t, const Converge& cv, hipStream_t s) {
     using Sh = Shape<VEC, ROWS>;
     dim3 grid;
     if (map.images) {
@@ -417,7 +453,7 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
         grid = dim3((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
     }
     KernelTimer timer("assign", s);
-    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t);
+    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t, cv);
     return hipGetLastError();
 }
 
@@ -425,6 +461,7 @@ struct VariantDesc {
     int vec, rows;
     size_t (*lds)(int);
     hipError_t (*launch)(const AssignImage&, const AssignTileMap&, int, int, long long,
+                         const Converge&,
                          hipStream_t);
 };
 
@@ -500,18 +537,20 @@ AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& 
 }
 
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int variant, hipStream_t s) {
+                         int variant, hipStream_t s, const Converge* cv) {
     if (!assign_variant_supported(variant, w, h, g.S)) variant = assign_default_variant(w, h, g.S);
     const AssignImage a = assign_image(ws, w, h, g, variant);
     const AssignTileMap none{nullptr, nullptr, nullptr};
-    return kVariants[variant - 1].launch(a, none, 0, g.S, t, s);
+    const Converge off{nullptr, 0, 0};
+    return kVariants[variant - 1].launch(a, none, 0, g.S, t, cv ? *cv : off, s);
 }
 
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
                                int variant, hipStream_t s) {
     if (variant < 1 || variant > kNumVariants || !map.images) return hipErrorInvalidValue;
     AssignImage unused{};
-    return kVariants[variant - 1].launch(unused, map, total_tiles, min_S, t, s);
+    const Converge off{nullptr, 0, 0};
+    return kVariants[variant - 1].launch(unused, map, total_tiles, min_S, t, off, s);
 }
 
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,
@@ -527,6 +566,17 @@ hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     if (e != hipSuccess) return e;
     KernelTimer t("energy_final", s);
     energy_final_kernel<<<1, kEnergyBlock, 0, s>>>(ws.partial, nb, static_cast<double>(n), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_converge_reset(long long* ctl, hipStream_t s) {
+    converge_reset_kernel<<<1, 64, 0, s>>>(ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_converge_result(const long long* ctl, int32_t max_iters, int32_t* out,
+                                  hipStream_t s) {
+    converge_result_kernel<<<1, 64, 0, s>>>(ctl, max_iters, out);
     return hipGetLastError();
 }
 

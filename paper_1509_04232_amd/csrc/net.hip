@@ -1,0 +1,1069 @@
+// The learned warm start: a 3x3 convolutional net (3 -> 32 -> 32 -> 9, ReLU
+// after the first two layers) that predicts, per pixel, which of the nine
+// grid cells around the pixel's own cell holds the centre the pixel ends up
+// with after plain SLIC, plus a learned per-phase bias P[(y mod S) S +
+// (x mod S)][9] on the logits (the convolutions alone cannot see where in
+// its cell a pixel lies).  Activations and convolution weights are bfloat16
+// (round to nearest even), accumulation FP32; every convolution runs on MFMA
+// (v_mfma_f32_16x16x32_bf16).
+//
+// Layouts.  Activations are NHWC over a batch of equally sized crops,
+// element ((n H + y) W + x) C + c, with C = 32 bf16 channels for the input
+// (3 used: L/100, a/128, b/128), both hidden layers and the gradients, and
+// C = 16 FP32 for the logits (9 used).  Zero padding at every crop border.
+// Parameters are one FP32 vector: W1[9][32][3], b1[32], W2[9][32][32], b2[32],
+// W3[9][9][32], b3[9], P[S*S][9], with tap = (dy + 1) * 3 + (dx + 1) reading
+// the input at (x + dx, y + dy).
+//
+// MFMA operands (v_mfma_f32_16x16x32_bf16, D = A B + C with A 16x32 and B
+// 32x16): lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
+// for j = 0..7 and holds D[4 (l / 16) + i][l % 16], i = 0..3.  The forward and
+// data-gradient convolutions take A = weights (out x in) and B = activations
+// (in x pixels); the weight gradients take A = output gradients (out x
+// pixels) and B = inputs (pixels x in).
+//
+// Training reductions are deterministic: each workgroup writes its partial
+// gradient, and one kernel sums the partials in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "slic_internal.h"
+
+namespace slic {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 32;   // hidden (and padded input) channels
+constexpr int kC3 = 9;   // classes
+constexpr int kOffW1 = 0, kOffB1 = 9 * kC * 3, kOffW2 = kOffB1 + kC;
+constexpr int kOffB2 = kOffW2 + 9 * kC * kC, kOffW3 = kOffB2 + kC;
+constexpr int kOffB3 = kOffW3 + 9 * kC3 * kC, kOffP = kOffB3 + kC3;
+constexpr int kMaxS = 32;
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite values)
+    return static_cast<unsigned short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short h) {
+    return __uint_as_float(static_cast<unsigned>(h) << 16);
+}
+__device__ __forceinline__ unsigned pack2(float lo, float hi) {
+    return static_cast<unsigned>(bf16_bits(lo)) | (static_cast<unsigned>(bf16_bits(hi)) << 16);
+}
+// The 32 bits starting 16 bits into the 64-bit value hi:lo.
+__device__ __forceinline__ unsigned mid16(unsigned hi, unsigned lo) {
+    return (lo >> 16) | (hi << 16);
+}
+
+struct NetCrop {
+    const float* L;
+    const float* A;
+    const float* B;
+    const int32_t* labels;
+    int img_w, img_h, ox, oy;
+};
+constexpr int kMaxCrops = 32;
+struct CropTable {
+    NetCrop c[kMaxCrops];
+};
+
+// bf16 weights in MFMA order: W1b[9][32][32] (inputs 3..31 zero),
+// W2b[9][32][32], W3b[9][16][32] (outputs 9..15 zero), and for the data
+// gradients the tap-flipped transposes W3t[t][c][o] = W3[8 - t][o][c]
+// (o = 9..31 zero) and W2t[t][c][o] = W2[8 - t][o][c].
+// W1i[o][K] is W1 unrolled over (tap, channel), K = 3 tap + c (27..31 zero),
+// for the fused inference kernel's single-MFMA first layer.
+struct NetWeights {
+    unsigned short *W1b, *W2b, *W3b, *W2t, *W3t, *W1i;
+};
+
+// ------------------------------------------------------------- weights
+
+__global__ void prepare_kernel(const float* __restrict__ p, NetWeights wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * kC * kC) return;
+    const int t = i / (kC * kC), o = (i / kC) % kC, c = i % kC;
+    wt.W1b[i] = c < 3 ? bf16_bits(p[kOffW1 + (t * kC + o) * 3 + c]) : 0;
+    wt.W2b[i] = bf16_bits(p[kOffW2 + i]);
+    // here o indexes the gradient's output (a forward input channel) and c
+    // its input (a forward output channel)
+    wt.W2t[i] = bf16_bits(p[kOffW2 + ((8 - t) * kC + c) * kC + o]);
+    wt.W3t[i] = c < kC3 ? bf16_bits(p[kOffW3 + ((8 - t) * kC3 + c) * kC + o]) : 0;
+    if (i < 9 * 16 * kC) {
+        const int t3 = i / (16 * kC), o3 = (i / kC) % 16, c3 = i % kC;
+        wt.W3b[i] = o3 < kC3 ? bf16_bits(p[kOffW3 + (t3 * kC3 + o3) * kC + c3]) : 0;
+    }
+    if (i < kC * kC) {
+        const int o1 = i / kC, k = i % kC;
+        wt.W1i[i] = k < 27 ? bf16_bits(p[kOffW1 + ((k / 3) * kC + o1) * 3 + k % 3]) : 0;
+    }
+}
+
+// --------------------------------------------------------------- input
+
+__global__ __launch_bounds__(256) void input_kernel(CropTable ct, int cw, int ch,
+                                                    unsigned short* __restrict__ x) {
+    const int per = cw * ch;
+    const int px = blockIdx.x * 256 + threadIdx.x;
+    const int n = blockIdx.y;
+    if (px >= per) return;
+    const NetCrop& c = ct.c[n];
+    const int gx = c.ox + px % cw, gy = c.oy + px / cw;
+    u32x4 v0 = {0u, 0u, 0u, 0u};
+    if (gx < c.img_w && gy < c.img_h) {
+        const size_t gi = static_cast<size_t>(gy) * c.img_w + gx;
+        v0.x = pack2(c.L[gi] / 100.0f, c.A[gi] / 128.0f);
+        v0.y = pack2(c.B[gi] / 128.0f, 0.0f);
+    }
+    u32x4* out = reinterpret_cast<u32x4*>(x + (static_cast<size_t>(n) * per + px) * kC);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    out[0] = v0;
+    out[1] = z;
+    out[2] = z;
+    out[3] = z;
+}
+
+// ------------------------------------------------- MFMA 3x3 convolution
+// 32 bf16 input channels.  A workgroup of four wavefronts covers kTW x 4
+// output pixels of one crop, one row per wavefront in N-tiles of 16 pixels;
+// the input tile and its one-pixel halo sit in LDS (pixel stride padded to
+// 40 elements).  MT tiles of 16 output channels.
+enum ConvMode { kFwdRelu = 0, kFwdLogits = 1, kBwdMasked = 2 };
+
+constexpr int kTW = 64, kTRows = 4;
+constexpr int kSW = kTW + 2, kSRows = kTRows + 2, kPS = 40;
+
+template <int MT, int MODE>
+__global__ __launch_bounds__(256) void conv_kernel(
+    const unsigned short* __restrict__ in, const unsigned short* __restrict__ Wb,
+    const float* __restrict__ bias, const float* __restrict__ P, CropTable ct, int S, int cw,
+    int ch, const unsigned short* __restrict__ mask, unsigned short* __restrict__ out16,
+    float* __restrict__ out32) {
+    __shared__ __align__(16) unsigned short tile[kSRows * kSW * kPS];
+    const int n = blockIdx.z;
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTRows;
+    const size_t base = static_cast<size_t>(n) * cw * ch;
+    for (int i = threadIdx.x; i < kSRows * kSW * 4; i += 256) {
+        const int q = i / 4, part = i % 4;
+        const int sx = x0 - 1 + q % kSW, sy = y0 - 1 + q / kSW;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (sx >= 0 && sy >= 0 && sx < cw && sy < ch)
+            v = reinterpret_cast<const u32x4*>(in + (base + static_cast<size_t>(sy) * cw + sx) * kC)[part];
+        *reinterpret_cast<u32x4*>(tile + q * kPS + part * 8) = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    bf16x8 wa[9][MT];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            wa[t][m] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(Wb + ((t * MT * 16 + m * 16 + row) * kC + kq * 8)));
+    __syncthreads();
+    const int y = y0 + wave;
+    if (y >= ch) return;
+    for (int nt = 0; nt < kTW / 16; ++nt) {
+        const int xs = x0 + nt * 16;
+        if (xs >= cw) break;
+        f32x4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            // staged position of input pixel (xs + row + dx, y + dy)
+            const int q = (wave + t / 3) * kSW + nt * 16 + row + t % 3;
+            const bf16x8 b =
+                __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(tile + q * kPS + kq * 8));
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][m], b, acc[m], 0, 0, 0);
+        }
+        // lane holds output channels 16 m + 4 kq + i of pixel xs + row
+        const int x = xs + row;
+        if (x >= cw) continue;
+        const size_t pi = base + static_cast<size_t>(y) * cw + x;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int o0 = m * 16 + kq * 4;
+            if constexpr (MODE == kFwdLogits) {
+                const NetCrop& c = ct.c[n];
+                const int ph = ((c.oy + y) % S) * S + (c.ox + x) % S;
+                f32x4 v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int o = o0 + i;
+                    v[i] = o < kC3 ? acc[m][i] + bias[o] + P[ph * kC3 + o] : 0.0f;
+                }
+                *reinterpret_cast<f32x4*>(out32 + pi * 16 + o0) = v;
+            } else {
+                // a hidden activation beyond the image is the zero padding
+                const NetCrop& c = ct.c[n];
+                const bool inside = c.ox + x < c.img_w && c.oy + y < c.img_h;
+                float r[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[m][i];
+                    if constexpr (MODE == kFwdRelu) {
+                        v = inside ? fmaxf(v + bias[o0 + i], 0.0f) : 0.0f;
+                    } else {  // through the ReLU that produced this layer's input
+                        if (!(bf16_float(mask[pi * kC + o0 + i]) > 0.0f)) v = 0.0f;
+                    }
+                    r[i] = v;
+                }
+                *reinterpret_cast<uint2*>(out16 + pi * kC + o0) =
+                    make_uint2(pack2(r[0], r[1]), pack2(r[2], r[3]));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ loss
+// Softmax cross-entropy per pixel with a target class (pixels beyond the
+// image have none); dz3 = softmax - onehot (unnormalised: every gradient is
+// scaled by 1 / count at the end), stored bf16 with 32 channels (9..31
+// zero).  Per workgroup: the sums of dz3 per class (b3) and per phase and
+// class (P), the loss sum and the count of pixels with a target.  The sums
+// of dz3 are taken in fixed point, rint(d * 2^18) in int32 (a workgroup's
+// kLossPx pixels stay below 2^31), so they do not depend on the order of
+// the LDS atomics and the gradient is the same on every run.
+constexpr int kLossPx = 4096;
+constexpr float kLossQ = 262144.0f;  // 2^18
+
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ logits,
+                                                   const int32_t* __restrict__ target, CropTable ct,
+                                                   int S, int cw, int ch, long long total,
+                                                   unsigned short* __restrict__ dz3,
+                                                   float* __restrict__ partial, int region,
+                                                   double* __restrict__ lossp) {
+    extern __shared__ int bins[];  // 9 + 9 S^2
+    __shared__ double red_l[256];
+    __shared__ int red_n[256];
+    for (int i = threadIdx.x; i < region; i += 256) bins[i] = 0;
+    __syncthreads();
+    const int per = cw * ch;
+    double l = 0.0;
+    int counted = 0;
+    int db3[kC3];
+#pragma unroll
+    for (int c = 0; c < kC3; ++c) db3[c] = 0;
+    for (int k = 0; k < kLossPx / 256; ++k) {
+        const long long pi = static_cast<long long>(blockIdx.x) * kLossPx + k * 256 + threadIdx.x;
+        if (pi >= total) break;
+        const int n = static_cast<int>(pi / per), px = static_cast<int>(pi % per);
+        const NetCrop& cr = ct.c[n];
+        const int gx = cr.ox + px % cw, gy = cr.oy + px / cw;
+        const float* lg = logits + pi * 16;
+        const int t = gx < cr.img_w && gy < cr.img_h ? target[pi] : -1;
+        unsigned packed[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) packed[j] = 0u;
+        if (t >= 0 && t < kC3) {
+            float v[kC3];
+            float mx = lg[0];
+#pragma unroll
+            for (int c = 0; c < kC3; ++c) {
+                v[c] = lg[c];
+                mx = fmaxf(mx, v[c]);
+            }
+            float lt = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kC3; ++c) lt = c == t ? v[c] : lt;
+            float se = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kC3; ++c) {
+                v[c] = expf(v[c] - mx);
+                se += v[c];
+            }
+            l += static_cast<double>(mx + logf(se) - lt);
+            ++counted;
+            const int ph = (gy % S) * S + gx % S;
+            float d[kC3];
+#pragma unroll
+            for (int c = 0; c < kC3; ++c) {
+                d[c] = v[c] / se - (c == t ? 1.0f : 0.0f);
+                const int q = static_cast<int>(rintf(d[c] * kLossQ));
+                db3[c] += q;
+                atomicAdd(&bins[kC3 + ph * kC3 + c], q);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) packed[j] = pack2(d[2 * j], d[2 * j + 1]);
+            packed[4] = pack2(d[8], 0.0f);
+        }
+        u32x4* o = reinterpret_cast<u32x4*>(dz3 + pi * kC);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            o[j] = u32x4{packed[4 * j], packed[4 * j + 1], packed[4 * j + 2], packed[4 * j + 3]};
+    }
+#pragma unroll
+    for (int c = 0; c < kC3; ++c) {
+        int v = db3[c];
+        for (int sh = 32; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&bins[c], v);
+    }
+    red_l[threadIdx.x] = l;
+    red_n[threadIdx.x] = counted;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            red_l[threadIdx.x] += red_l[threadIdx.x + off];
+            red_n[threadIdx.x] += red_n[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    float* out = partial + static_cast<size_t>(blockIdx.x) * region;
+    for (int i = threadIdx.x; i < region; i += 256) out[i] = static_cast<float>(bins[i]) / kLossQ;
+    if (threadIdx.x == 0) {
+        lossp[2 * blockIdx.x] = red_l[0];
+        lossp[2 * blockIdx.x + 1] = static_cast<double>(red_n[0]);
+    }
+}
+
+// ------------------------------------------------------- weight gradient
+// dW[t][o][i] = sum over pixels p of dz[p][o] * a[p + d_t][i] (and, with a
+// bias, db[o] = sum dz[p][o]) over a strip of kGW x kGStrip pixels of one
+// crop, kGR rows at a time.  dz and the input (with halo) are staged in LDS
+// channel-blocked: element (r, x, c) at ((r * chunks + x / 8) * 32 + c) * 8 +
+// x % 8, so a lane's eight pixels of one channel are one 16-byte read; the
+// one-pixel shifts of the taps are funnel shifts of neighbouring words.
+// Wavefront w takes output tile m and input tile ni (two output tiles x two
+// input tiles for MO = 2; for MO = 1 wavefronts 2, 3 take the odd rows and
+// add into 0, 1 at the end), all nine taps.
+constexpr int kGW = 64, kGR = 4, kGStrip = 32;
+constexpr int kGZChunks = kGW / 8;       // dz: columns x0 .. x0 + 63
+constexpr int kGAChunks = kGW / 8 + 2;   // input: columns x0 - 8 .. x0 + 71
+
+template <int MO>
+__global__ __launch_bounds__(256) void wgrad_kernel(const unsigned short* __restrict__ dz,
+                                                    const unsigned short* __restrict__ a, int cw,
+                                                    int ch, int cout, int cin_keep, int has_bias,
+                                                    float* __restrict__ partial, int region) {
+    __shared__ __align__(16) unsigned short sdz[kGR * kGZChunks * kC * 8];
+    __shared__ __align__(16) unsigned short sa[(kGR + 2) * kGAChunks * kC * 8];
+    const int n = blockIdx.z;
+    const int x0 = blockIdx.x * kGW;
+    const size_t base = static_cast<size_t>(n) * cw * ch;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int m = MO == 2 ? wave >> 1 : 0;
+    const int ni = wave & 1;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+
+    for (int chunk = 0; chunk < kGStrip / kGR; ++chunk) {
+        const int y0 = blockIdx.y * kGStrip + chunk * kGR;
+        if (y0 >= ch) break;
+        for (int i = threadIdx.x; i < kGR * kGW * 4; i += 256) {
+            const int q = i >> 2, part = i & 3;
+            const int r = q / kGW, xx = q % kGW;
+            const int x = x0 + xx, y = y0 + r;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (x < cw && y < ch)
+                v = reinterpret_cast<const u32x4*>(dz + (base + static_cast<size_t>(y) * cw + x) * kC)[part];
+            unsigned short* d = sdz + ((r * kGZChunks + xx / 8) * kC + part * 8) * 8 + xx % 8;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                d[(2 * j) * 8] = static_cast<unsigned short>(v[j] & 0xFFFFu);
+                d[(2 * j + 1) * 8] = static_cast<unsigned short>(v[j] >> 16);
+            }
+        }
+        for (int i = threadIdx.x; i < (kGR + 2) * kGAChunks * 8 * 4; i += 256) {
+            const int q = i >> 2, part = i & 3;
+            const int r = q / (kGAChunks * 8), xs = q % (kGAChunks * 8);
+            const int x = x0 - 8 + xs, y = y0 - 1 + r;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (x >= 0 && y >= 0 && x < cw && y < ch)
+                v = reinterpret_cast<const u32x4*>(a + (base + static_cast<size_t>(y) * cw + x) * kC)[part];
+            unsigned short* d = sa + ((r * kGAChunks + xs / 8) * kC + part * 8) * 8 + xs % 8;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                d[(2 * j) * 8] = static_cast<unsigned short>(v[j] & 0xFFFFu);
+                d[(2 * j + 1) * 8] = static_cast<unsigned short>(v[j] >> 16);
+            }
+        }
+        __syncthreads();
+        if (has_bias && static_cast<int>(threadIdx.x) < cout) {
+            for (int r = 0; r < kGR; ++r)
+                for (int c8 = 0; c8 < kGZChunks; ++c8)
+                    for (int e = 0; e < 8; ++e)
+                        bsum += bf16_float(sdz[((r * kGZChunks + c8) * kC + threadIdx.x) * 8 + e]);
+        }
+        for (int r = (MO == 2 ? 0 : wave >> 1); r < kGR; r += (MO == 2 ? 1 : 2)) {
+#pragma unroll
+            for (int kk = 0; kk < kGW / 32; ++kk) {
+                const int c8 = kk * 4 + kq;  // chunk of this lane's 8 pixels
+                const bf16x8 av = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(
+                                sdz + ((r * kGZChunks + c8) * kC + m * 16 + row) * 8));
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const unsigned short* srow = sa + (((r + dy) * kGAChunks) * kC + ni * 16 + row) * 8;
+                    const u32x4 w1 = *reinterpret_cast<const u32x4*>(srow + (c8 + 1) * kC * 8);
+                    const unsigned w0 = *reinterpret_cast<const unsigned*>(srow + c8 * kC * 8 + 6);
+                    const unsigned w2 = *reinterpret_cast<const unsigned*>(srow + (c8 + 2) * kC * 8);
+                    const u32x4 bl = {mid16(w1.x, w0), mid16(w1.y, w1.x), mid16(w1.z, w1.y),
+                                      mid16(w1.w, w1.z)};
+                    const u32x4 br = {mid16(w1.y, w1.x), mid16(w1.z, w1.y), mid16(w1.w, w1.z),
+                                      mid16(w2, w1.w)};
+                    acc[dy * 3 + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av, __builtin_bit_cast(bf16x8, bl), acc[dy * 3 + 0], 0, 0, 0);
+                    acc[dy * 3 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av, __builtin_bit_cast(bf16x8, w1), acc[dy * 3 + 1], 0, 0, 0);
+                    acc[dy * 3 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av, __builtin_bit_cast(bf16x8, br), acc[dy * 3 + 2], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float* out = partial + static_cast<size_t>(blockIdx.z * gridDim.y * gridDim.x +
+                                               blockIdx.y * gridDim.x + blockIdx.x) * region;
+    if (MO == 1) {  // fold the odd-row wavefronts into the even-row ones
+        float* red = reinterpret_cast<float*>(sa);
+        if (wave >= 2)
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[((wave - 2) * 36 + t * 4 + i) * 64 + lane] = acc[t][i];
+        __syncthreads();
+        if (wave < 2)
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[t][i] += red[(wave * 36 + t * 4 + i) * 64 + lane];
+    }
+    if (MO == 2 || wave < 2) {
+        const int in = ni * 16 + row;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = m * 16 + kq * 4 + i;
+                if (o < cout && in < cin_keep) out[(t * cout + o) * cin_keep + in] = acc[t][i];
+            }
+    }
+    if (has_bias && static_cast<int>(threadIdx.x) < cout) out[9 * cout * cin_keep + threadIdx.x] = bsum;
+}
+
+// Sum of the partial gradients in block order, scaled by 1 / count.
+struct GradRegions {
+    const float* part[4];
+    int start[4], size[4], nblk[4];
+};
+
+__global__ void reduce_kernel(GradRegions r, int count, const double* __restrict__ lossp,
+                              int nloss, float* __restrict__ grad, double* __restrict__ loss) {
+    __shared__ double s_inv;
+    if (threadIdx.x == 0) {
+        double tl = 0.0, tn = 0.0;
+        for (int b = 0; b < nloss; ++b) {
+            tl += lossp[2 * b];
+            tn += lossp[2 * b + 1];
+        }
+        s_inv = tn > 0.0 ? 1.0 / tn : 0.0;
+        if (blockIdx.x == 0 && loss) *loss = tl * s_inv;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int j = 0;
+    while (j < 3 && i >= r.start[j] + r.size[j]) ++j;
+    const int li = i - r.start[j], sz = r.size[j];
+    const float* p = r.part[j];
+    double s = 0.0;
+    for (int b = 0; b < r.nblk[j]; ++b) s += static_cast<double>(p[static_cast<size_t>(b) * sz + li]);
+    grad[i] = static_cast<float>(s * s_inv);
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, int count, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Training targets from converged labels: the class (dy + 1) * 3 + (dx + 1)
+// of the label's cell relative to the pixel's cell; -1 if not a neighbour or
+// outside the image.
+__global__ void targets_kernel(CropTable ct, int S, int cw, int ch, int32_t* __restrict__ target) {
+    const int px = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (px >= cw * ch) return;
+    const NetCrop& c = ct.c[n];
+    const int gx = c.ox + px % cw, gy = c.oy + px / cw;
+    int t = -1;
+    if (gx < c.img_w && gy < c.img_h) {
+        const int ns_c = (c.img_w + S - 1) / S;
+        const int k = c.labels[static_cast<size_t>(gy) * c.img_w + gx];
+        const int dy = k / ns_c - gy / S, dx = k % ns_c - gx / S;
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) t = (dy + 1) * 3 + (dx + 1);
+    }
+    target[static_cast<size_t>(n) * cw * ch + px] = t;
+}
+
+__global__ void export_logits_kernel(const float* __restrict__ lg16, long long total,
+                                     float* __restrict__ out) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total * kC3) return;
+    out[i] = lg16[(i / kC3) * 16 + i % kC3];
+}
+
+// ------------------------------------------ fused inference (warm start)
+// The whole net plus the decoding for a kFW x kFH tile of output pixels of
+// one image, with every activation in LDS: the input over the tile and a
+// 3-pixel halo, the first hidden layer over a 2-pixel halo, the second over
+// a 1-pixel halo (regions flattened row-major, computed in N-tiles of 16
+// consecutive pixels).  Activations outside the image are zero, which is the
+// zero padding of every layer.  The first layer is one MFMA per 16 pixels:
+// its K runs over (tap, channel) pairs.  The logits stay in registers: the
+// argmax combines the four lanes that hold a pixel's classes, and the decoded
+// label enters the cluster sums as in the association kernel (LDS bins,
+// then one global add per non-empty bin); the workgroup holding a cell's
+// first pixel clears that cluster's next accumulator.
+constexpr int kFW = 32, kFH = 8;
+constexpr int kXW = kFW + 6, kXH = kFH + 6;      // input region
+constexpr int kA1W = kFW + 4, kA1H = kFH + 4;    // first hidden layer region
+constexpr int kA2W = kFW + 2, kA2H = kFH + 2;    // second hidden layer region
+constexpr int kA1N = (kA1W * kA1H + 15) / 16;    // N-tiles
+constexpr int kA2N = (kA2W * kA2H + 15) / 16;
+constexpr int kON = kFW * kFH / 16;
+constexpr int kFusedX = kXW * kXH * 4;           // u16 elements
+constexpr int kFusedA1 = kA1W * kA1H * kPS;
+constexpr int kPS2 = 32;                         // second layer's pixel stride
+constexpr int kFusedA2 = kA2N * 16 * kPS2;
+constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2) * sizeof(unsigned short);
+static_assert(kFusedLds <= 64 * 1024, "fused net tile exceeds 64 KiB of LDS");
+
+struct FusedImage {
+    const float *L, *A, *B;
+    int w, h, S, ns_c, ns_r;
+    const float *b1, *b2, *b3, *P;
+    int32_t* labels;
+    long long *sums_acc, *sums_next;
+};
+
+__global__ __launch_bounds__(256) void net_fused_kernel(FusedImage g, NetWeights wt) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned short* sx = reinterpret_cast<unsigned short*>(smem);
+    unsigned short* sa1 = sx + kFusedX;
+    unsigned short* sa2 = sa1 + kFusedA1;
+    const int x0 = blockIdx.x * kFW, y0 = blockIdx.y * kFH;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+
+    // ---- input region (bf16 L/100, a/128, b/128, 0)
+    for (int q = threadIdx.x; q < kXW * kXH; q += 256) {
+        const int gx = x0 - 3 + q % kXW, gy = y0 - 3 + q / kXW;
+        uint2 v = make_uint2(0u, 0u);
+        if (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h) {
+            const size_t gi = static_cast<size_t>(gy) * g.w + gx;
+            v = make_uint2(pack2(g.L[gi] / 100.0f, g.A[gi] / 128.0f), pack2(g.B[gi] / 128.0f, 0.0f));
+        }
+        *reinterpret_cast<uint2*>(sx + q * 4) = v;
+    }
+    __syncthreads();
+
+    // ---- first layer: K = 3 tap + c, one MFMA per 16 pixels and 16 outputs
+    {
+        bf16x8 w1[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            w1[m] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(wt.W1i + (m * 16 + row) * kC + kq * 8));
+        int koff[8];  // offset of this lane's K values inside the input region
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kq * 8 + j, t = k / 3;
+            koff[j] = k < 27 ? ((t / 3) * kXW + t % 3) * 4 + k % 3 : -1;
+        }
+        float bias[2][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bias[m][i] = g.b1[m * 16 + kq * 4 + i];
+        for (int nt = wave; nt < kA1N; nt += 4) {
+            const int p = min(nt * 16 + row, kA1W * kA1H - 1);
+            const int r = p / kA1W, c = p % kA1W;
+            const unsigned short* src = sx + (r * kXW + c) * 4;
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                b[j] = __builtin_bit_cast(__bf16, koff[j] >= 0 ? src[koff[j] < 0 ? 0 : koff[j]]
+                                                                : static_cast<unsigned short>(0));
+            const int gx = x0 - 2 + c, gy = y0 - 2 + r;
+            const bool inside = nt * 16 + row < kA1W * kA1H && gx >= 0 && gy >= 0 && gx < g.w &&
+                                gy < g.h;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], b, acc, 0, 0, 0);
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bias[m][i], 0.0f) : 0.0f;
+                if (nt * 16 + row < kA1W * kA1H)
+                    *reinterpret_cast<uint2*>(sa1 + p * kPS + m * 16 + kq * 4) =
+                        make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- second layer over the 1-pixel halo
+    {
+        bf16x8 w2[9][2];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                w2[t][m] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(wt.W2b + ((t * 32 + m * 16 + row) * kC + kq * 8)));
+        float bias[2][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bias[m][i] = g.b2[m * 16 + kq * 4 + i];
+        for (int nt = wave; nt < kA2N; nt += 4) {
+            const int pr = nt * 16 + row;
+            const int p = min(pr, kA2W * kA2H - 1);
+            const int r = p / kA2W, c = p % kA2W;
+            f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int q = (r + t / 3) * kA1W + c + t % 3;
+                const bf16x8 b = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(sa1 + q * kPS + kq * 8));
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][m], b, acc[m], 0, 0, 0);
+            }
+            const int gx = x0 - 1 + c, gy = y0 - 1 + r;
+            const bool inside = gx >= 0 && gy >= 0 && gx < g.w && gy < g.h;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    v[i] = inside ? fmaxf(acc[m][i] + bias[m][i], 0.0f) : 0.0f;
+                *reinterpret_cast<uint2*>(sa2 + pr * kPS2 + m * 16 + kq * 4) =
+                    make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- LDS bins for the decoded labels (over the first layer's region)
+    const int S = g.S;
+    const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
+    const int gx_hi = (min(x0 + kFW, g.w) - 1) / S + 1;
+    const int gy_hi = (min(y0 + kFH, g.h) - 1) / S + 1;
+    const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
+    unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
+    int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
+    for (int i = threadIdx.x; i < ncells; i += 256) {
+        const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
+        for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
+        const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
+        const int k = in_grid ? cy * g.ns_c + cx : -1;
+        kidx[i] = k;
+        if (in_grid && (cx * S) / kFW == static_cast<int>(blockIdx.x) &&
+            (cy * S) / kFH == static_cast<int>(blockIdx.y)) {
+            long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
+            for (int j = 0; j < kSumStride; ++j) z[j] = 0;
+        }
+    }
+    __syncthreads();
+
+    // ---- third layer, phase bias, argmax, decode, accumulate
+    {
+        bf16x8 w3[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+            w3[t] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(wt.W3b + ((t * 16 + row) * kC + kq * 8)));
+        const float scale = static_cast<float>(1 << kQShift);
+        for (int nt = wave; nt < kON; nt += 4) {
+            const int p = nt * 16 + row;
+            const int r = p / kFW, c = p % kFW;
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int q = (r + t / 3) * kA2W + c + t % 3;
+                const bf16x8 b = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(sa2 + q * kPS2 + kq * 8));
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[t], b, acc, 0, 0, 0);
+            }
+            const int x = x0 + c, y = y0 + r;
+            const int ph = (y % S) * S + x % S;
+            // this lane's classes 4 kq .. 4 kq + 3: best value, lowest class on ties
+            float bv = -__builtin_huge_valf();
+            int bc = 15;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = kq * 4 + i;
+                if (o < kC3) {
+                    const float v = acc[i] + g.b3[o] + g.P[ph * kC3 + o];
+                    if (v > bv) {
+                        bv = v;
+                        bc = o;
+                    }
+                }
+            }
+#pragma unroll
+            for (int sh = 16; sh <= 32; sh <<= 1) {
+                const float ov = __shfl_xor(bv, sh);
+                const int oc = __shfl_xor(bc, sh);
+                if (ov > bv || (ov == bv && oc < bc)) {
+                    bv = ov;
+                    bc = oc;
+                }
+            }
+            if (kq == 0 && x < g.w && y < g.h) {
+                const int cy = min(max(y / S + bc / 3 - 1, 0), g.ns_r - 1);
+                const int cx = min(max(x / S + bc % 3 - 1, 0), g.ns_c - 1);
+                const size_t pi = static_cast<size_t>(y) * g.w + x;
+                g.labels[pi] = cy * g.ns_c + cx;
+                const int cell = (cy - gy_lo) * ncx + (cx - gx_lo);
+                atomicAdd(bins + cell, static_cast<unsigned long long>(
+                                           static_cast<long long>(rintf(g.L[pi] * scale))));
+                atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(
+                                                    static_cast<long long>(rintf(g.A[pi] * scale))));
+                atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(
+                                                        static_cast<long long>(rintf(g.B[pi] * scale))));
+                atomicAdd(bins + 3 * ncells + cell,
+                          static_cast<unsigned long long>(c) |
+                              (static_cast<unsigned long long>(r) << 20) | (1ull << 40));
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncells; i += 256) {
+        const unsigned long long p = bins[3 * ncells + i];
+        const long long cnt = static_cast<long long>(p >> 40);
+        if (cnt == 0) continue;
+        unsigned long long* s =
+            reinterpret_cast<unsigned long long*>(g.sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
+        atomicAdd(s + 0, bins[i]);
+        atomicAdd(s + 1, bins[ncells + i]);
+        atomicAdd(s + 2, bins[2 * ncells + i]);
+        atomicAdd(s + 3, static_cast<unsigned long long>(static_cast<long long>(p & 0xFFFFFull) + cnt * x0));
+        atomicAdd(s + 4,
+                  static_cast<unsigned long long>(static_cast<long long>((p >> 20) & 0xFFFFFull) + cnt * y0));
+        atomicAdd(s + 5, static_cast<unsigned long long>(cnt));
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct NetWs {
+    unsigned short *x, *a1, *a2, *dz3, *dz2;  // dz1 reuses dz3, dz2 the logits
+    float* logits;
+    NetWeights wt;
+    float *part_w1, *part_w2, *part_w3, *part_loss;
+    double* lossp;
+    int nb_grad, nb_loss, loss_region;
+};
+
+int grad_blocks(int n, int cw, int ch) {
+    return ((cw + kGW - 1) / kGW) * ((ch + kGStrip - 1) / kGStrip) * n;
+}
+int loss_blocks(long long total) { return static_cast<int>((total + kLossPx - 1) / kLossPx); }
+
+// Workspace parts by mode: kWeights (the bf16 weight copies), kForward
+// (+ activations and logits), kTraining (+ gradients and partial sums).
+enum NetMode { kWeights = 0, kForward = 1, kTraining = 2 };
+
+size_t net_layout(int n, int cw, int ch, int S, int mode, NetWs* nw, char* base) {
+    const size_t P = static_cast<size_t>(n) * cw * ch;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    NetWs w{};
+    w.wt.W1b = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
+    w.wt.W2b = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
+    w.wt.W3b = reinterpret_cast<unsigned short*>(take(9 * 16 * kC * 2));
+    w.wt.W2t = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
+    w.wt.W3t = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
+    w.wt.W1i = reinterpret_cast<unsigned short*>(take(kC * kC * 2));
+    if (mode >= kForward) {
+        w.x = reinterpret_cast<unsigned short*>(take(P * kC * 2));
+        w.a1 = reinterpret_cast<unsigned short*>(take(P * kC * 2));
+        w.a2 = reinterpret_cast<unsigned short*>(take(P * kC * 2));
+        w.logits = reinterpret_cast<float*>(take(P * 16 * sizeof(float)));
+        w.dz2 = reinterpret_cast<unsigned short*>(w.logits);
+    }
+    if (mode >= kTraining) {
+        w.dz3 = reinterpret_cast<unsigned short*>(take(P * kC * 2));
+        w.nb_grad = grad_blocks(n, cw, ch);
+        w.nb_loss = loss_blocks(static_cast<long long>(P));
+        w.loss_region = kC3 + kC3 * S * S;
+        w.part_w1 = reinterpret_cast<float*>(take(static_cast<size_t>(w.nb_grad) * (kOffW2 - kOffW1) * 4));
+        w.part_w2 = reinterpret_cast<float*>(take(static_cast<size_t>(w.nb_grad) * (kOffW3 - kOffW2) * 4));
+        w.part_w3 = reinterpret_cast<float*>(take(static_cast<size_t>(w.nb_grad) * (kOffB3 - kOffW3) * 4));
+        w.part_loss = reinterpret_cast<float*>(take(static_cast<size_t>(w.nb_loss) * w.loss_region * 4));
+        w.lossp = reinterpret_cast<double*>(take(static_cast<size_t>(w.nb_loss) * 2 * sizeof(double)));
+    }
+    if (nw) *nw = w;
+    return off;
+}
+
+bool shape_ok(int n, int cw, int ch, int S) {
+    return n >= 1 && n <= kMaxCrops && cw >= 1 && ch >= 1 && cw <= (1 << 16) && ch <= (1 << 16) &&
+           static_cast<long long>(n) * cw * ch < (1ll << 31) / kC && S >= 1 && S <= kMaxS;
+}
+
+bool device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+bool crops_ok(const slic_net_crop* crops, int n, bool need_lab, bool need_labels) {
+    if (!crops) return false;
+    for (int i = 0; i < n; ++i) {
+        const slic_net_crop& c = crops[i];
+        if (c.img_w < 1 || c.img_h < 1 || c.ox < 0 || c.oy < 0 || c.ox >= c.img_w || c.oy >= c.img_h)
+            return false;
+        if (static_cast<long long>(c.img_w) * c.img_h >= (1ll << 31)) return false;
+        if (need_lab && (!device_ptr(c.d_L) || !device_ptr(c.d_a) || !device_ptr(c.d_b))) return false;
+        if (need_labels && !device_ptr(c.d_labels)) return false;
+    }
+    return true;
+}
+
+CropTable crop_table(const slic_net_crop* crops, int n) {
+    CropTable t;
+    std::memset(&t, 0, sizeof(t));
+    for (int i = 0; i < n; ++i) {
+        t.c[i] = NetCrop{crops[i].d_L, crops[i].d_a, crops[i].d_b, crops[i].d_labels,
+                         crops[i].img_w, crops[i].img_h, crops[i].ox, crops[i].oy};
+    }
+    return t;
+}
+
+hipError_t enqueue_forward(const NetWs& nw, const CropTable& ct, int n, int cw, int ch, int S,
+                           const float* params, hipStream_t s) {
+    {
+        KernelTimer t("net_prepare", s);
+        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt);
+    }
+    const int per = cw * ch;
+    {
+        KernelTimer t("net_input", s);
+        input_kernel<<<dim3((per + 255) / 256, n), 256, 0, s>>>(ct, cw, ch, nw.x);
+    }
+    const dim3 grid((cw + kTW - 1) / kTW, (ch + kTRows - 1) / kTRows, n);
+    {
+        KernelTimer t("net_conv1", s);
+        conv_kernel<2, kFwdRelu><<<grid, 256, 0, s>>>(nw.x, nw.wt.W1b, params + kOffB1, nullptr, ct,
+                                                      S, cw, ch, nullptr, nw.a1, nullptr);
+    }
+    {
+        KernelTimer t("net_conv2", s);
+        conv_kernel<2, kFwdRelu><<<grid, 256, 0, s>>>(nw.a1, nw.wt.W2b, params + kOffB2, nullptr, ct,
+                                                      S, cw, ch, nullptr, nw.a2, nullptr);
+    }
+    {
+        KernelTimer t("net_conv3", s);
+        conv_kernel<1, kFwdLogits><<<grid, 256, 0, s>>>(nw.a2, nw.wt.W3b, params + kOffB3,
+                                                        params + kOffP, ct, S, cw, ch, nullptr,
+                                                        nullptr, nw.logits);
+    }
+    return hipGetLastError();
+}
+
+hipError_t enqueue_backward(const NetWs& nw, const CropTable& ct, int n, int cw, int ch, int S,
+                            const int32_t* target, float* grad, double* loss, hipStream_t s) {
+    const long long total = static_cast<long long>(n) * cw * ch;
+    {
+        KernelTimer t("net_loss", s);
+        loss_kernel<<<nw.nb_loss, 256, nw.loss_region * sizeof(int), s>>>(
+            nw.logits, target, ct, S, cw, ch, total, nw.dz3, nw.part_loss, nw.loss_region, nw.lossp);
+    }
+    const dim3 ggrid((cw + kGW - 1) / kGW, (ch + kGStrip - 1) / kGStrip, n);
+    const dim3 cgrid((cw + kTW - 1) / kTW, (ch + kTRows - 1) / kTRows, n);
+    {
+        KernelTimer t("net_wgrad3", s);
+        wgrad_kernel<1><<<ggrid, 256, 0, s>>>(nw.dz3, nw.a2, cw, ch, kC3, kC, 0, nw.part_w3,
+                                              kOffB3 - kOffW3);
+    }
+    {
+        KernelTimer t("net_dgrad3", s);
+        conv_kernel<2, kBwdMasked><<<cgrid, 256, 0, s>>>(nw.dz3, nw.wt.W3t, nullptr, nullptr, ct, S,
+                                                         cw, ch, nw.a2, nw.dz2, nullptr);
+    }
+    {
+        KernelTimer t("net_wgrad2", s);
+        wgrad_kernel<2><<<ggrid, 256, 0, s>>>(nw.dz2, nw.a1, cw, ch, kC, kC, 1, nw.part_w2,
+                                              kOffW3 - kOffW2);
+    }
+    unsigned short* dz1 = nw.dz3;
+    {
+        KernelTimer t("net_dgrad2", s);
+        conv_kernel<2, kBwdMasked><<<cgrid, 256, 0, s>>>(nw.dz2, nw.wt.W2t, nullptr, nullptr, ct, S,
+                                                         cw, ch, nw.a1, dz1, nullptr);
+    }
+    {
+        KernelTimer t("net_wgrad1", s);
+        wgrad_kernel<2><<<ggrid, 256, 0, s>>>(dz1, nw.x, cw, ch, kC, 3, 1, nw.part_w1,
+                                              kOffW2 - kOffW1);
+    }
+    GradRegions r;
+    r.part[0] = nw.part_w1;
+    r.start[0] = kOffW1;
+    r.size[0] = kOffW2 - kOffW1;
+    r.nblk[0] = nw.nb_grad;
+    r.part[1] = nw.part_w2;
+    r.start[1] = kOffW2;
+    r.size[1] = kOffW3 - kOffW2;
+    r.nblk[1] = nw.nb_grad;
+    r.part[2] = nw.part_w3;
+    r.start[2] = kOffW3;
+    r.size[2] = kOffB3 - kOffW3;
+    r.nblk[2] = nw.nb_grad;
+    r.part[3] = nw.part_loss;
+    r.start[3] = kOffB3;
+    r.size[3] = nw.loss_region;
+    r.nblk[3] = nw.nb_loss;
+    const int count = kOffP + kC3 * S * S;
+    {
+        KernelTimer t("net_reduce", s);
+        reduce_kernel<<<(count + 255) / 256, 256, 0, s>>>(r, count, nw.lossp, nw.nb_loss, grad, loss);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t warm_net_bytes(int32_t w, int32_t h, int32_t S) {
+    if (!shape_ok(1, w, h, S)) return 0;
+    return net_layout(1, w, h, S, kWeights, nullptr, nullptr);
+}
+
+hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                             const float* params, void* net_ws, hipStream_t s) {
+    NetWs nw;
+    net_layout(1, w, h, g.S, kWeights, &nw, static_cast<char*>(net_ws));
+    {
+        KernelTimer t("net_prepare", s);
+        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt);
+    }
+    const size_t ring = static_cast<size_t>(g.K) * kSumStride;
+    FusedImage f{ws.L, ws.A, ws.B, w, h, g.S, g.ns_c, g.ns_r,
+                 params + kOffB1, params + kOffB2, params + kOffB3, params + kOffP,
+                 ws.labels, ws.sums, ws.sums + ring};
+    KernelTimer t("net_fused", s);
+    net_fused_kernel<<<dim3((w + kFW - 1) / kFW, (h + kFH - 1) / kFH), 256, kFusedLds, s>>>(f, nw.wt);
+    return hipGetLastError();
+}
+
+}  // namespace slic
+
+using namespace slic;
+
+extern "C" {
+
+int32_t slic_net_param_count(int32_t S) {
+    if (S < 1 || S > kMaxS) return 0;
+    return kOffP + kC3 * S * S;
+}
+
+size_t slic_net_workspace_bytes(int32_t n_crops, int32_t crop_w, int32_t crop_h, int32_t S) {
+    if (!shape_ok(n_crops, crop_w, crop_h, S)) return 0;
+    return net_layout(n_crops, crop_w, crop_h, S, kTraining, nullptr, nullptr);
+}
+
+int slic_net_forward(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                     int32_t S, const float* d_params, float* d_logits, void* hip_stream,
+                     void* d_ws, size_t ws_bytes) {
+    if (!shape_ok(n_crops, crop_w, crop_h, S) || !crops_ok(crops, n_crops, true, false))
+        return SLIC_EINVAL;
+    if (!device_ptr(d_params) || !device_ptr(d_logits) || !device_ptr(d_ws) ||
+        reinterpret_cast<uintptr_t>(d_ws) % kAlign != 0 ||
+        ws_bytes < net_layout(n_crops, crop_w, crop_h, S, kForward, nullptr, nullptr))
+        return SLIC_EINVAL;
+    NetWs nw;
+    net_layout(n_crops, crop_w, crop_h, S, kForward, &nw, static_cast<char*>(d_ws));
+    const CropTable ct = crop_table(crops, n_crops);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (enqueue_forward(nw, ct, n_crops, crop_w, crop_h, S, d_params, s) != hipSuccess) return SLIC_EHIP;
+    const long long total = static_cast<long long>(n_crops) * crop_w * crop_h;
+    {
+        KernelTimer t("net_export", s);
+        export_logits_kernel<<<static_cast<unsigned>((total * kC3 + 255) / 256), 256, 0, s>>>(
+            nw.logits, total, d_logits);
+    }
+    return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
+}
+
+int slic_net_loss_grad(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                       int32_t S, const float* d_params, const int32_t* d_target, float* d_grad,
+                       double* d_loss, void* hip_stream, void* d_ws, size_t ws_bytes) {
+    if (!shape_ok(n_crops, crop_w, crop_h, S) || !crops_ok(crops, n_crops, true, false))
+        return SLIC_EINVAL;
+    if (!device_ptr(d_params) || !device_ptr(d_target) || !device_ptr(d_grad) || !device_ptr(d_ws) ||
+        (d_loss && !device_ptr(d_loss)) || reinterpret_cast<uintptr_t>(d_ws) % kAlign != 0 ||
+        ws_bytes < net_layout(n_crops, crop_w, crop_h, S, kTraining, nullptr, nullptr))
+        return SLIC_EINVAL;
+    NetWs nw;
+    net_layout(n_crops, crop_w, crop_h, S, kTraining, &nw, static_cast<char*>(d_ws));
+    const CropTable ct = crop_table(crops, n_crops);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (enqueue_forward(nw, ct, n_crops, crop_w, crop_h, S, d_params, s) != hipSuccess) return SLIC_EHIP;
+    if (enqueue_backward(nw, ct, n_crops, crop_w, crop_h, S, d_target, d_grad, d_loss, s) != hipSuccess)
+        return SLIC_EHIP;
+    return SLIC_OK;
+}
+
+int slic_net_targets(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w, int32_t crop_h,
+                     int32_t S, int32_t* d_target, void* hip_stream) {
+    if (!shape_ok(n_crops, crop_w, crop_h, S) || !crops_ok(crops, n_crops, false, true) ||
+        !device_ptr(d_target))
+        return SLIC_EINVAL;
+    const CropTable ct = crop_table(crops, n_crops);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int per = crop_w * crop_h;
+    targets_kernel<<<dim3((per + 255) / 256, n_crops), 256, 0, s>>>(ct, S, crop_w, crop_h, d_target);
+    return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
+}
+
+int slic_net_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t count,
+                  int32_t step, float lr, float beta1, float beta2, float eps, void* hip_stream) {
+    if (count < 1 || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !device_ptr(d_params) ||
+        !device_ptr(d_grad) || !device_ptr(d_m) || !device_ptr(d_v))
+        return SLIC_EINVAL;
+    const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
+    const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    adam_kernel<<<(count + 255) / 256, 256, 0, s>>>(d_params, d_grad, d_m, d_v, count, lr, beta1,
+                                                    beta2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
+}
+
+}  // extern "C"

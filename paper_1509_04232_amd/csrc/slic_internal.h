@@ -36,6 +36,7 @@ struct Workspace {
     int32_t *ccl0, *ccl1, *ccl2, *ccl3;  // N each, connectivity scratch
     int32_t* scan;       // block totals of the connectivity prefix sum
     double* partial;     // per-block energy partial sums
+    long long* ctl;      // convergence control: residual ring [3], stop flag, iterations
     int32_t n_scan_blocks, n_energy_blocks;
 };
 
@@ -94,12 +95,26 @@ struct AssignTileMap {
     const int* tile_first;
 };
 
+// Convergence stop (Section 2): with ctl set, association launch t also sums
+// the quantised L1 shift of the centres it updates into ctl[t % 3]; launch t
+// of a run that began at t_first exits at once if a previous launch stopped
+// the run (ctl[3] != 0) or if t > t_first and the shift of launch t - 1 is
+// below limit, in which case it sets ctl[3] = 1 and ctl[4] = t - t_first.
+struct Converge {
+    long long* ctl;
+    long long limit;
+    long long t_first;
+};
+hipError_t launch_converge_reset(long long* ctl, hipStream_t s);
+hipError_t launch_converge_result(const long long* ctl, int32_t max_iters, int32_t* out,
+                                  hipStream_t s);
+
 // Association launch number t (0: the first, with the seeds as centres;
 // t >= 1 also completes the centre update of the previous launch).
 // variant: launch shape 1..assign_variant_count(); an unsupported value
 // falls back to assign_default_variant.
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int variant, hipStream_t s);
+                         int variant, hipStream_t s, const Converge* cv = nullptr);
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
                                int variant, hipStream_t s);
 AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant);
@@ -115,6 +130,16 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
                                hipStream_t s);
 hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out, int32_t* counts,
                                  hipStream_t s);
+
+// Learned warm start (net.hip).  warm_net_bytes: the net's forward
+// buffers for one w x h image at step S (0 if unsupported).
+// launch_warm_start: after launch_lab_seed, runs the net on ws.L/A/B,
+// writes the decoded labels to ws.labels, accumulates them into the first
+// accumulator buffer (as association launch 0 would) and clears the second,
+// so that association launch 1 starts from the net's labels.
+size_t warm_net_bytes(int32_t w, int32_t h, int32_t S);
+hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                             const float* params, void* net_ws, hipStream_t s);
 
 // Kernel timing: while enabled, a KernelTimer brackets a launch with HIP
 // events on the launch stream.
@@ -140,5 +165,6 @@ struct slic_ctx {
     int device;
     int variant;    // association launch variant
     int64_t t;      // association launches so far
-    int state;      // 0: k-means state valid, 1: connectivity done, 2: poisoned
+    int state;      // 0: k-means state valid, 1: connectivity done, 2: poisoned,
+                    // 3: stopped by the convergence rule (final)
 };
