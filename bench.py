@@ -343,9 +343,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=600,
+    ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps of the warm-start net in the c5 leg")
-    ap.add_argument("--train-images", type=int, default=64,
+    ap.add_argument("--train-images", type=int, default=128,
                     help="c5 training images for the warm-start net")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (PMC calibration)")
