@@ -250,9 +250,11 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
                               None, e_plain[i:].data_ptr() if with_energy else None, None, stream,
                               ws_plain.data_ptr(), ws_plain.numel())
 
+    prepared = slic.warm.prepare(net.params, S)
+
     def run_warm():
         for i in range(n_eval):
-            slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), net.params.data_ptr(), warm_iters,
+            slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), prepared.data_ptr(), warm_iters,
                                    0, lab_warm[i].data_ptr(), None, e_warm[i:].data_ptr(), None,
                                    stream, ws_warm.data_ptr(), ws_warm.numel())
 
@@ -350,8 +352,9 @@ def main() -> int:
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (PMC calibration)")
     ap.add_argument("--workload-only", default=None, metavar="NAME",
-                    help="profiling mode: run warmup+steps frames of workload NAME (c1, c2, c3) "
-                         "and the optional copy, print one line per phase, no JSON")
+                    help="profiling mode: run warmup+steps frames of workload NAME (c1, c2, c3, "
+                         "or c5warm: the warm-start path) and the optional copy, print one line "
+                         "per phase, no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the SLIC path has no multi-GPU mode "
@@ -369,6 +372,21 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.workload_only == "c5warm":
+        # the warm-start path (untrained parameters: the timing does not
+        # depend on their values) on the first 640x480 evaluation image
+        from synth.configs import warm_eval_workload
+        w = warm_eval_workload(0)
+        rgb = torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev)
+        p = slic.Params(w.width, w.height, S=w.S, m=w.m)
+        net = slic.warm.Net(w.S, 1, 16, 16, seed=1)
+        ws = torch.empty(slic.slic_warm_workspace_bytes(p.c()), dtype=torch.uint8, device=dev)
+        prepared = slic.warm.prepare(net.params, w.S)
+        for _ in range(args.warmup + args.steps):
+            slic.warm.warm_segment(rgb, p, prepared, 2, workspace=ws)
+        torch.cuda.synchronize()
+        print(f"ran {args.warmup + args.steps} warm-start frames of {w.name}", flush=True)
+        return 0
     if args.workload_only:
         w = synth.WORKLOADS[args.workload_only]
         f = Frame(slic, w, dev)

@@ -266,24 +266,33 @@ int slic_net_targets(const slic_net_crop* crops, int32_t n_crops, int32_t crop_w
 int slic_net_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t count,
                   int32_t step, float lr, float beta1, float beta2, float eps, void* hip_stream);
 
+/* A prepared net for inference: the bf16 weight copies in the layouts the
+ * kernels read, followed by the FP32 parameters.  slic_net_prepared_bytes
+ * is the size of that device buffer (the same for every S; it must be
+ * 256-byte aligned); slic_net_prepare fills it from d_params
+ * (slic_net_param_count(S) floats, enqueued on the stream).  Prepare once
+ * per parameter set, then run any number of frames with the same step S. */
+size_t slic_net_prepared_bytes(void);
+int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_stream);
+
 /* Warm-started segmentation.  slic_warm_init converts d_rgb, seeds the
- * centres exactly as slic_init does, runs the net on the whole image and
- * takes its decoded label map as the first association (in place of
+ * centres exactly as slic_init does, runs the prepared net d_net (prepared
+ * for the step S of p, 1 <= S <= 32) on the whole image in one fused kernel
+ * and takes its decoded label map as the first association (in place of
  * slic_init's association with the seeds).  The context then behaves as one
- * from slic_init: slic_iterate(ctx, n) runs n rounds of (update, associate),
- * the first update using the net's labels; a cluster that no pixel chose
- * keeps its seed.  d_net_params: slic_net_param_count(S) floats for the
- * step S of p.  Workspace: slic_warm_workspace_bytes(p) bytes (the
- * segmentation's plus the net's forward buffers, about 256 bytes per pixel).
+ * from slic_init: slic_iterate(ctx, n) runs n rounds of (update,
+ * associate), the first update using the net's labels; a cluster that no
+ * pixel chose keeps its seed.  Workspace: slic_warm_workspace_bytes(p)
+ * (equal to slic_workspace_bytes(p); 0 if S is beyond the net's range).
  * slic_warm_segment runs init, n_iters rounds, the energy (d_energy may be
  * NULL) and, with enforce, connectivity, like slic_segment.
  * Gate: the warm result is meant to replace plain SLIC only where its energy
  * is at most 1.01 times plain SLIC's; that comparison is the caller's (it
  * needs the plain energy). */
 size_t slic_warm_workspace_bytes(const slic_params* p);
-int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
-                   const float* d_net_params, void* hip_stream, void* d_ws, size_t ws_bytes);
-int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
+int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, const void* d_net,
+                   void* hip_stream, void* d_ws, size_t ws_bytes);
+int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const void* d_net,
                       int32_t n_iters, int32_t enforce, int32_t* d_labels, float* d_centres,
                       double* d_energy, int32_t* d_n_segments, void* hip_stream, void* d_ws,
                       size_t ws_bytes);

@@ -23,7 +23,8 @@ from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, S
                    slic_timing_enable, slic_timing_read, slic_workspace_bytes,
                    SlicNetCrop, slic_net_adam, slic_net_forward, slic_net_loss_grad,
                    slic_net_param_count, slic_net_targets, slic_net_workspace_bytes,
-                   slic_warm_init, slic_warm_segment, slic_warm_workspace_bytes)
+                   slic_net_prepare, slic_net_prepared_bytes, slic_warm_init, slic_warm_segment,
+                   slic_warm_workspace_bytes)
 
 __all__ = [
     "Params", "Context", "Batch", "segment", "workspace_for", "SlicError", "SlicParams",
@@ -79,26 +80,26 @@ def workspace_for(p: Params, device=None) -> torch.Tensor:
 
 
 class Context:
-    """A slic_ctx: slic_init on construction (slic_warm_init when the net's
-    parameters are given), then iterate / enforce / get."""
+    """A slic_ctx: slic_init on construction (slic_warm_init when a prepared
+    net, ``warm.prepare``, is given), then iterate / enforce / get."""
 
     def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None,
-                 net_params: torch.Tensor | None = None):
+                 net: torch.Tensor | None = None):
         _check_rgb(rgb, p)
         self.params = p
         self._cp = p.c()
         self.stream = stream
         self._rgb = rgb  # kept alive until the conversion has run
-        if net_params is None:
+        if net is None:
             self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
             self.ctx = slic_init(self._cp, rgb.data_ptr(), _stream(stream), self.ws.data_ptr(),
                                  self.ws.numel())
         else:
             self.ws = workspace if workspace is not None else torch.empty(
                 slic_warm_workspace_bytes(self._cp), dtype=torch.uint8, device=rgb.device)
-            self._net = net_params
-            self.ctx = slic_warm_init(self._cp, rgb.data_ptr(), net_params.data_ptr(),
-                                      _stream(stream), self.ws.data_ptr(), self.ws.numel())
+            self._net = net
+            self.ctx = slic_warm_init(self._cp, rgb.data_ptr(), net.data_ptr(), _stream(stream),
+                                      self.ws.data_ptr(), self.ws.numel())
         self.device = rgb.device
 
     def iterate(self, n: int) -> "Context":

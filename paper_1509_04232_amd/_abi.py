@@ -83,6 +83,8 @@ _SIGS = {
     "slic_net_targets": ([_CP, _I, _I, _I, _I, _P, _P], ctypes.c_int),
     "slic_net_adam": ([_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                        ctypes.c_float, _P], ctypes.c_int),
+    "slic_net_prepared_bytes": ([], ctypes.c_size_t),
+    "slic_net_prepare": ([_I, _P, _P, _P], ctypes.c_int),
     "slic_warm_workspace_bytes": ([_PP], ctypes.c_size_t),
     "slic_warm_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_warm_segment": ([_PP, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t],
@@ -306,6 +308,14 @@ def slic_net_adam(d_params: int, d_grad: int, d_m: int, d_v: int, count: int, st
                              stream), "slic_net_adam")
 
 
+def slic_net_prepared_bytes() -> int:
+    return int(lib.slic_net_prepared_bytes())
+
+
+def slic_net_prepare(S: int, d_params: int, d_net: int, stream: int) -> None:
+    _check(lib.slic_net_prepare(S, d_params, d_net, stream), "slic_net_prepare")
+
+
 def slic_warm_workspace_bytes(p: SlicParams) -> int:
     n = lib.slic_warm_workspace_bytes(ctypes.byref(p))
     if n == 0:
@@ -313,17 +323,17 @@ def slic_warm_workspace_bytes(p: SlicParams) -> int:
     return int(n)
 
 
-def slic_warm_init(p: SlicParams, d_rgb: int, d_net_params: int, stream: int, d_ws: int,
+def slic_warm_init(p: SlicParams, d_rgb: int, d_net: int, stream: int, d_ws: int,
                    ws_bytes: int) -> int:
     ctx = _P()
-    _check(lib.slic_warm_init(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_net_params, stream,
+    _check(lib.slic_warm_init(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_net, stream,
                               d_ws, ws_bytes), "slic_warm_init")
     return int(ctx.value)
 
 
-def slic_warm_segment(p: SlicParams, d_rgb: int, d_net_params: int, n_iters: int, enforce: int,
+def slic_warm_segment(p: SlicParams, d_rgb: int, d_net: int, n_iters: int, enforce: int,
                       d_labels: int, d_centres: int | None, d_energy: int | None,
                       d_n_segments: int | None, stream: int, d_ws: int, ws_bytes: int) -> None:
-    _check(lib.slic_warm_segment(ctypes.byref(p), d_rgb, d_net_params, n_iters, enforce, d_labels,
+    _check(lib.slic_warm_segment(ctypes.byref(p), d_rgb, d_net, n_iters, enforce, d_labels,
                                  d_centres, d_energy, d_n_segments, stream, d_ws, ws_bytes),
            "slic_warm_segment")

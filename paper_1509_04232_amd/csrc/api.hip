@@ -533,60 +533,49 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
 
 namespace {
 
-// Byte offset of the net's buffers in a warm-start workspace (after the
-// segmentation's own), or 0 if the parameters do not support the net.
-size_t warm_split(const slic_params* p, Grid* g) {
-    if (!params_ok(p)) return 0;
-    compute_grid(p, g);
-    if (warm_net_bytes(p->width, p->height, g->S) == 0) return 0;
-    return align_up(workspace_layout(p->width, p->height, *g, nullptr, nullptr));
-}
-
 // slic_init with the net's decoded labels as the first association.
-hipError_t enqueue_warm_init(slic_ctx* c, const uint8_t* rgb, const float* net_params,
-                             void* net_ws) {
+hipError_t enqueue_warm_init(slic_ctx* c, const uint8_t* rgb, const void* d_net) {
     const slic_params& p = c->p;
     hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
                                    (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
     if (e != hipSuccess) return e;
     c->t = 0;
-    e = launch_warm_start(c->ws, p.width, p.height, c->g, net_params, net_ws, c->stream);
+    e = launch_warm_start(c->ws, p.width, p.height, c->g, d_net, c->stream);
     if (e == hipSuccess) c->t = 1;
     return e;
 }
 
-int check_warm_args(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
-                    void* d_ws, size_t ws_bytes, size_t* split) {
+int check_warm_args(const slic_params* p, const uint8_t* d_rgb, const void* d_net, void* d_ws,
+                    size_t ws_bytes) {
+    if (!params_ok(p) || !d_rgb || !d_net || !d_ws || !aligned(d_ws) || !aligned(d_net))
+        return SLIC_EINVAL;
     Grid g;
-    *split = warm_split(p, &g);
-    if (*split == 0 || !d_rgb || !d_net_params || !d_ws || !aligned(d_ws)) return SLIC_EINVAL;
-    if (ws_bytes < *split + warm_net_bytes(p->width, p->height, g.S)) return SLIC_EINVAL;
+    compute_grid(p, &g);
+    if (!warm_supported(g.S) || ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
     int rc = check_buffers(d_rgb, d_ws);
     if (rc) return rc;
-    return check_device_ptr(d_net_params);
+    return check_device_ptr(d_net);
 }
 
 }  // namespace
 
 size_t slic_warm_workspace_bytes(const slic_params* p) {
+    if (!params_ok(p)) return 0;
     Grid g;
-    const size_t split = warm_split(p, &g);
-    if (split == 0) return 0;
-    return split + warm_net_bytes(p->width, p->height, g.S);
+    compute_grid(p, &g);
+    return warm_supported(g.S) ? slic_workspace_bytes(p) : 0;
 }
 
-int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
-                   const float* d_net_params, void* hip_stream, void* d_ws, size_t ws_bytes) {
+int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, const void* d_net,
+                   void* hip_stream, void* d_ws, size_t ws_bytes) {
     if (!out) return SLIC_EINVAL;
     *out = nullptr;
-    size_t split = 0;
-    int rc = check_warm_args(p, d_rgb, d_net_params, d_ws, ws_bytes, &split);
+    int rc = check_warm_args(p, d_rgb, d_net, d_ws, ws_bytes);
     if (rc) return rc;
     slic_ctx* c = new (std::nothrow) slic_ctx;
     if (!c) return SLIC_ENOMEM;
     bind(c, p, d_ws, hip_stream);
-    if (hipGetDevice(&c->device) != hipSuccess ||
-        enqueue_warm_init(c, d_rgb, d_net_params, static_cast<char*>(d_ws) + split) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess || enqueue_warm_init(c, d_rgb, d_net) != hipSuccess) {
         delete c;
         return SLIC_EHIP;
     }
@@ -594,20 +583,18 @@ int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
     return SLIC_OK;
 }
 
-int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const float* d_net_params,
+int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const void* d_net,
                       int32_t n_iters, int32_t enforce, int32_t* d_labels, float* d_centres,
                       double* d_energy, int32_t* d_n_segments, void* hip_stream, void* d_ws,
                       size_t ws_bytes) {
     if (n_iters < 0 || !d_labels) return SLIC_EINVAL;
-    size_t split = 0;
-    int rc = check_warm_args(p, d_rgb, d_net_params, d_ws, ws_bytes, &split);
+    int rc = check_warm_args(p, d_rgb, d_net, d_ws, ws_bytes);
     if (rc) return rc;
     if ((rc = check_device_ptr(d_labels)) != 0) return rc;
     slic_ctx c;
     bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;
-    if (enqueue_warm_init(&c, d_rgb, d_net_params, static_cast<char*>(d_ws) + split) != hipSuccess)
-        return SLIC_EHIP;
+    if (enqueue_warm_init(&c, d_rgb, d_net) != hipSuccess) return SLIC_EHIP;
     if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
         launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)

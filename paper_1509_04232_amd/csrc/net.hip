@@ -46,16 +46,18 @@ constexpr int kOffB2 = kOffW2 + 9 * kC * kC, kOffW3 = kOffB2 + kC;
 constexpr int kOffB3 = kOffW3 + 9 * kC3 * kC, kOffP = kOffB3 + kC3;
 constexpr int kMaxS = 32;
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> bf16, round to nearest even (gfx950's v_cvt_pk_bf16_f32).
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite values)
-    return static_cast<unsigned short>(u >> 16);
+    return __builtin_bit_cast(unsigned short, static_cast<__bf16>(f));
 }
 __device__ __forceinline__ float bf16_float(unsigned short h) {
     return __uint_as_float(static_cast<unsigned>(h) << 16);
 }
 __device__ __forceinline__ unsigned pack2(float lo, float hi) {
-    return static_cast<unsigned>(bf16_bits(lo)) | (static_cast<unsigned>(bf16_bits(hi)) << 16);
+    const bf16x2 v = {static_cast<__bf16>(lo), static_cast<__bf16>(hi)};
+    return __builtin_bit_cast(unsigned, v);
 }
 // The 32 bits starting 16 bits into the 64-bit value hi:lo.
 __device__ __forceinline__ unsigned mid16(unsigned hi, unsigned lo) {
@@ -78,16 +80,16 @@ struct CropTable {
 // W2b[9][32][32], W3b[9][16][32] (outputs 9..15 zero), and for the data
 // gradients the tap-flipped transposes W3t[t][c][o] = W3[8 - t][o][c]
 // (o = 9..31 zero) and W2t[t][c][o] = W2[8 - t][o][c].
-// W1i[o][K] is W1 unrolled over (tap, channel), K = 3 tap + c (27..31 zero),
-// for the fused inference kernel's single-MFMA first layer.
 struct NetWeights {
-    unsigned short *W1b, *W2b, *W3b, *W2t, *W3t, *W1i;
+    unsigned short *W1b, *W2b, *W3b, *W2t, *W3t;
 };
 
 // ------------------------------------------------------------- weights
 
-__global__ void prepare_kernel(const float* __restrict__ p, NetWeights wt) {
+__global__ void prepare_kernel(const float* __restrict__ p, NetWeights wt, int count,
+                               float* __restrict__ copy) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (copy && i < count) copy[i] = p[i];
     if (i >= 9 * kC * kC) return;
     const int t = i / (kC * kC), o = (i / kC) % kC, c = i % kC;
     wt.W1b[i] = c < 3 ? bf16_bits(p[kOffW1 + (t * kC + o) * 3 + c]) : 0;
@@ -99,10 +101,6 @@ __global__ void prepare_kernel(const float* __restrict__ p, NetWeights wt) {
     if (i < 9 * 16 * kC) {
         const int t3 = i / (16 * kC), o3 = (i / kC) % 16, c3 = i % kC;
         wt.W3b[i] = o3 < kC3 ? bf16_bits(p[kOffW3 + (t3 * kC3 + o3) * kC + c3]) : 0;
-    }
-    if (i < kC * kC) {
-        const int o1 = i / kC, k = i % kC;
-        wt.W1i[i] = k < 27 ? bf16_bits(p[kOffW1 + ((k / 3) * kC + o1) * 3 + k % 3]) : 0;
     }
 }
 
@@ -525,17 +523,23 @@ __global__ void export_logits_kernel(const float* __restrict__ lg16, long long t
 }
 
 // ------------------------------------------ fused inference (warm start)
-// The whole net plus the decoding for a kFW x kFH tile of output pixels of
-// one image, with every activation in LDS: the input over the tile and a
-// 3-pixel halo, the first hidden layer over a 2-pixel halo, the second over
-// a 1-pixel halo (regions flattened row-major, computed in N-tiles of 16
-// consecutive pixels).  Activations outside the image are zero, which is the
-// zero padding of every layer.  The first layer is one MFMA per 16 pixels:
-// its K runs over (tap, channel) pairs.  The logits stay in registers: the
-// argmax combines the four lanes that hold a pixel's classes, and the decoded
-// label enters the cluster sums as in the association kernel (LDS bins,
-// then one global add per non-empty bin); the workgroup holding a cell's
-// first pixel clears that cluster's next accumulator.
+// The whole net plus the decoding, tile by tile (kFW x kFH output pixels),
+// with every activation in LDS: the input over the tile and a 3-pixel halo,
+// the first hidden layer over a 2-pixel halo, the second over a 1-pixel halo
+// (regions flattened row-major and computed in N-tiles of 16 consecutive
+// pixels; hidden pixels padded to 80 bytes so the 16 lanes reading one
+// 16-byte chunk of 16 consecutive pixels hit distinct banks, and every tap
+// is a constant offset from the lane's base address).  Activations outside
+// the image are zero, which is the zero padding of every layer.  The first
+// layer takes K over (tap, channel) pairs with the input stored as 4
+// channels (the fourth zero): taps 0..7 in one MFMA, tap 8 in a second.
+// Workgroups are persistent: each loads the weights once (the first two
+// layers into registers, the third into LDS) and walks tiles blockIdx.x,
+// + gridDim.x, ...  The logits stay in registers: the argmax combines the
+// four lanes that hold a pixel's classes, and the decoded label enters the
+// cluster sums as in the association kernel (LDS bins, then one global add
+// per non-empty bin); the workgroup holding a cell's first pixel clears that
+// cluster's next accumulator.
 constexpr int kFW = 32, kFH = 8;
 constexpr int kXW = kFW + 6, kXH = kFH + 6;      // input region
 constexpr int kA1W = kFW + 4, kA1H = kFH + 4;    // first hidden layer region
@@ -545,10 +549,14 @@ constexpr int kA2N = (kA2W * kA2H + 15) / 16;
 constexpr int kON = kFW * kFH / 16;
 constexpr int kFusedX = kXW * kXH * 4;           // u16 elements
 constexpr int kFusedA1 = kA1W * kA1H * kPS;
-constexpr int kPS2 = 32;                         // second layer's pixel stride
-constexpr int kFusedA2 = kA2N * 16 * kPS2;
-constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2) * sizeof(unsigned short);
-static_assert(kFusedLds <= 64 * 1024, "fused net tile exceeds 64 KiB of LDS");
+constexpr int kFusedA2 = kA2N * 16 * kPS;
+constexpr int kFusedW3 = 9 * 16 * kC;            // third layer's weights
+constexpr int kFusedTab = 2 * (kFW + kFH);       // x / S, x % S, y / S, y % S
+constexpr int kFusedLab = 3 * kFW * kFH;         // the tile's own CIELAB, FP32
+constexpr int kXSlots = (kXW * kXH + 255) / 256; // input pixels per thread
+constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2 + kFusedW3) * sizeof(unsigned short) +
+                             kFusedTab * sizeof(int) + kFusedLab * sizeof(float);
+static_assert(2 * kFusedLds <= 160 * 1024, "two fused-net workgroups must fit one CU's LDS");
 
 struct FusedImage {
     const float *L, *A, *B;
@@ -556,160 +564,250 @@ struct FusedImage {
     const float *b1, *b2, *b3, *P;
     int32_t* labels;
     long long *sums_acc, *sums_next;
+    int tiles_x, n_tiles;
 };
 
-__global__ __launch_bounds__(256) void net_fused_kernel(FusedImage g, NetWeights wt) {
+__global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeights wt) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned short* sx = reinterpret_cast<unsigned short*>(smem);
     unsigned short* sa1 = sx + kFusedX;
     unsigned short* sa2 = sa1 + kFusedA1;
-    const int x0 = blockIdx.x * kFW, y0 = blockIdx.y * kFH;
+    unsigned short* sw3 = sa2 + kFusedA2;
+    int* tab = reinterpret_cast<int*>(sw3 + kFusedW3);
+    float* slab = reinterpret_cast<float*>(tab + kFusedTab);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
+    const int S = g.S;
 
-    // ---- input region (bf16 L/100, a/128, b/128, 0)
-    for (int q = threadIdx.x; q < kXW * kXH; q += 256) {
-        const int gx = x0 - 3 + q % kXW, gy = y0 - 3 + q / kXW;
-        uint2 v = make_uint2(0u, 0u);
-        if (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h) {
-            const size_t gi = static_cast<size_t>(gy) * g.w + gx;
-            v = make_uint2(pack2(g.L[gi] / 100.0f, g.A[gi] / 128.0f), pack2(g.B[gi] / 128.0f, 0.0f));
-        }
-        *reinterpret_cast<uint2*>(sx + q * 4) = v;
-    }
-    __syncthreads();
-
-    // ---- first layer: K = 3 tap + c, one MFMA per 16 pixels and 16 outputs
-    {
-        bf16x8 w1[2];
+    // ---- weights and biases, once per workgroup
+    for (int i = threadIdx.x; i < kFusedW3 / 8; i += 256)
+        reinterpret_cast<u32x4*>(sw3)[i] = reinterpret_cast<const u32x4*>(wt.W3b)[i];
+    // first layer: A[o][k] with k = 4 tap + c for taps 0..7, and tap 8 alone
+    bf16x8 w1[2][2], w2[9][2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-            w1[m] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(wt.W1i + (m * 16 + row) * kC + kq * 8));
-        int koff[8];  // offset of this lane's K values inside the input region
+    for (int m = 0; m < 2; ++m) {
+        bf16x8 a, b;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int k = kq * 8 + j, t = k / 3;
-            koff[j] = k < 27 ? ((t / 3) * kXW + t % 3) * 4 + k % 3 : -1;
+            const int k = kq * 8 + j, t = k >> 2, c = k & 3;
+            a[j] = __builtin_bit_cast(__bf16, c < 3 ? wt.W1b[(t * kC + m * 16 + row) * kC + c]
+                                                    : static_cast<unsigned short>(0));
+            b[j] = __builtin_bit_cast(__bf16, (kq == 0 && j < 3) ? wt.W1b[(8 * kC + m * 16 + row) * kC + j]
+                                                                  : static_cast<unsigned short>(0));
         }
-        float bias[2][4];
+        w1[m][0] = a;
+        w1[m][1] = b;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
+            w2[t][m] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(wt.W2b + ((t * 32 + m * 16 + row) * kC + kq * 8)));
+    float bias1[2][4], bias2[2][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bias[m][i] = g.b1[m * 16 + kq * 4 + i];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bias1[m][i] = g.b1[m * 16 + kq * 4 + i];
+            bias2[m][i] = g.b2[m * 16 + kq * 4 + i];
+        }
+    // this lane's two first-layer taps 2 kq, 2 kq + 1 as input-region offsets
+    const int t0 = 2 * kq, t1 = 2 * kq + 1;
+    const int xoff0 = ((t0 / 3) * kXW + t0 % 3) * 4, xoff1 = ((t1 / 3) * kXW + t1 % 3) * 4;
+    const float scale = static_cast<float>(1 << kQShift);
+
+    // the input region of a tile, loaded one tile ahead so that its latency
+    // overlaps the previous tile's work (zeros outside the image)
+    float pf[kXSlots][3];
+    auto prefetch = [&](int tile) {
+        const int px0 = (tile % g.tiles_x) * kFW - 3, py0 = (tile / g.tiles_x) * kFH - 3;
+#pragma unroll
+        for (int j = 0; j < kXSlots; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            const int gx = px0 + q % kXW, gy = py0 + q / kXW;
+            pf[j][0] = pf[j][1] = pf[j][2] = 0.0f;
+            if (q < kXW * kXH && gx >= 0 && gy >= 0 && gx < g.w && gy < g.h) {
+                const size_t gi = static_cast<size_t>(gy) * g.w + gx;
+                pf[j][0] = g.L[gi];
+                pf[j][1] = g.A[gi];
+                pf[j][2] = g.B[gi];
+            }
+        }
+    };
+    if (static_cast<int>(blockIdx.x) < g.n_tiles) prefetch(blockIdx.x);
+
+    for (int tile = blockIdx.x; tile < g.n_tiles; tile += gridDim.x) {
+        const int x0 = (tile % g.tiles_x) * kFW, y0 = (tile / g.tiles_x) * kFH;
+        // every halo pixel inside the image: no padding checks in the epilogues
+        const bool interior = x0 >= 3 && y0 >= 3 && x0 + kFW + 3 <= g.w && y0 + kFH + 3 <= g.h;
+        __syncthreads();  // the previous tile's bins are flushed
+
+        // ---- input region (bf16 L/100, a/128, b/128, 0), the tile's own
+        // CIELAB in FP32, decode tables; then the next tile's loads
+#pragma unroll
+        for (int j = 0; j < kXSlots; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q >= kXW * kXH) continue;
+            *reinterpret_cast<uint2*>(sx + q * 4) =
+                make_uint2(pack2(pf[j][0] / 100.0f, pf[j][1] / 128.0f), pack2(pf[j][2] / 128.0f, 0.0f));
+            const int r = q / kXW - 3, c = q % kXW - 3;
+            if (r >= 0 && r < kFH && c >= 0 && c < kFW) {
+                float* d = slab + (r * kFW + c) * 3;
+                d[0] = pf[j][0];
+                d[1] = pf[j][1];
+                d[2] = pf[j][2];
+            }
+        }
+        if (threadIdx.x < kFW) {
+            const int x = x0 + threadIdx.x;
+            tab[threadIdx.x] = x / S;
+            tab[kFW + threadIdx.x] = x % S;
+        } else if (threadIdx.x < kFW + kFH) {
+            const int y = y0 + threadIdx.x - kFW;
+            tab[kFW + threadIdx.x] = y / S;                 // 2 kFW + r
+            tab[kFW + kFH + threadIdx.x] = y % S;           // 2 kFW + kFH + r
+        }
+        if (tile + static_cast<int>(gridDim.x) < g.n_tiles) prefetch(tile + gridDim.x);
+        __syncthreads();
+
+        // ---- first layer
         for (int nt = wave; nt < kA1N; nt += 4) {
-            const int p = min(nt * 16 + row, kA1W * kA1H - 1);
+            const int pr = nt * 16 + row;
+            const int p = min(pr, kA1W * kA1H - 1);
             const int r = p / kA1W, c = p % kA1W;
             const unsigned short* src = sx + (r * kXW + c) * 4;
-            bf16x8 b;
+            const uint2 v0 = *reinterpret_cast<const uint2*>(src + xoff0);
+            const uint2 v1 = *reinterpret_cast<const uint2*>(src + xoff1);
+            const uint2 v8 = *reinterpret_cast<const uint2*>(src + (2 * kXW + 2) * 4);
+            const u32x4 bw = {v0.x, v0.y, v1.x, v1.y};
+            const u32x4 b8 = {v8.x, v8.y, 0u, 0u};
+            f32x4 acc[2];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                b[j] = __builtin_bit_cast(__bf16, koff[j] >= 0 ? src[koff[j] < 0 ? 0 : koff[j]]
-                                                                : static_cast<unsigned short>(0));
+            for (int m = 0; m < 2; ++m) {
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    w1[m][0], __builtin_bit_cast(bf16x8, bw), f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    w1[m][1], __builtin_bit_cast(bf16x8, b8), acc[m], 0, 0, 0);
+            }
             const int gx = x0 - 2 + c, gy = y0 - 2 + r;
-            const bool inside = nt * 16 + row < kA1W * kA1H && gx >= 0 && gy >= 0 && gx < g.w &&
-                                gy < g.h;
+            const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
+            if (pr < kA1W * kA1H) {
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[m], b, acc, 0, 0, 0);
-                float v[4];
+                for (int m = 0; m < 2; ++m) {
+                    float o[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bias[m][i], 0.0f) : 0.0f;
-                if (nt * 16 + row < kA1W * kA1H)
+                    for (int i = 0; i < 4; ++i)
+                        o[i] = inside ? fmaxf(acc[m][i] + bias1[m][i], 0.0f) : 0.0f;
                     *reinterpret_cast<uint2*>(sa1 + p * kPS + m * 16 + kq * 4) =
-                        make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+                        make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
+                }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // ---- second layer over the 1-pixel halo
-    {
-        bf16x8 w2[9][2];
+        // ---- second layer over the 1-pixel halo, two N-tiles at a time
+        for (int pp = wave; 2 * pp < kA2N; pp += 4) {
+            int pr[2], r[2], c[2];
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
+            for (int u = 0; u < 2; ++u) {
+                pr[u] = (2 * pp + u) * 16 + row;
+                const int p = min(pr[u], kA2W * kA2H - 1);
+                r[u] = p / kA2W;
+                c[u] = p % kA2W;
+            }
+            const unsigned short* base[2] = {sa1 + (r[0] * kA1W + c[0]) * kPS + kq * 8,
+                                             sa1 + (r[1] * kA1W + c[1]) * kPS + kq * 8};
+            f32x4 acc[2][2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
-                w2[t][m] = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const u32x4*>(wt.W2b + ((t * 32 + m * 16 + row) * kC + kq * 8)));
-        float bias[2][4];
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) bias[m][i] = g.b2[m * 16 + kq * 4 + i];
-        for (int nt = wave; nt < kA2N; nt += 4) {
-            const int pr = nt * 16 + row;
-            const int p = min(pr, kA2W * kA2H - 1);
-            const int r = p / kA2W, c = p % kA2W;
-            f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+                for (int m = 0; m < 2; ++m) acc[u][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const int q = (r + t / 3) * kA1W + c + t % 3;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const bf16x8 b = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4*>(base[u] + ((t / 3) * kA1W + t % 3) * kPS));
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+                        acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][m], b, acc[u][m], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (2 * pp + u >= kA2N) break;
+                const int gx = x0 - 1 + c[u], gy = y0 - 1 + r[u];
+                const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    float o[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        o[i] = inside ? fmaxf(acc[u][m][i] + bias2[m][i], 0.0f) : 0.0f;
+                    *reinterpret_cast<uint2*>(sa2 + pr[u] * kPS + m * 16 + kq * 4) =
+                        make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- LDS bins for the decoded labels (over the first layer's region)
+        const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
+        const int gx_hi = (min(x0 + kFW, g.w) - 1) / S + 1;
+        const int gy_hi = (min(y0 + kFH, g.h) - 1) / S + 1;
+        const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
+        unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
+        int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
+        for (int i = threadIdx.x; i < ncells; i += 256) {
+            const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
+            for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
+            const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
+            const int k = in_grid ? cy * g.ns_c + cx : -1;
+            kidx[i] = k;
+            if (in_grid && (cx * S) / kFW == x0 / kFW && (cy * S) / kFH == y0 / kFH) {
+                long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
+                for (int j = 0; j < kSumStride; ++j) z[j] = 0;
+            }
+        }
+        __syncthreads();
+
+        // ---- third layer, phase bias, argmax, decode, accumulate
+        static_assert(kON % 4 == 0, "output tiles split evenly over four wavefronts");
+        constexpr int kPer = kON / 4;
+        float pb[kPer][4];  // b3 + P of this lane's classes, loaded before the MFMAs
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int p = (wave + 4 * u) * 16 + row;
+            const int ph = tab[2 * kFW + kFH + p / kFW] * S + tab[kFW + p % kFW];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = kq * 4 + i;
+                pb[u][i] = o < kC3 ? g.b3[o] + g.P[ph * kC3 + o] : 0.0f;
+            }
+        }
+        f32x4 accs[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) accs[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const bf16x8 w3 = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(sw3 + (t * 16 + row) * kC + kq * 8));
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                // output pixel p = (wave + 4 u) * 16 + row; rows of 32 hold two N-tiles
+                const int p = (wave + 4 * u) * 16 + row;
+                const unsigned short* bp = sa2 + ((p / kFW) * kA2W + p % kFW) * kPS + kq * 8;
                 const bf16x8 b = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const u32x4*>(sa1 + q * kPS + kq * 8));
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][m], b, acc[m], 0, 0, 0);
-            }
-            const int gx = x0 - 1 + c, gy = y0 - 1 + r;
-            const bool inside = gx >= 0 && gy >= 0 && gx < g.w && gy < g.h;
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                float v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    v[i] = inside ? fmaxf(acc[m][i] + bias[m][i], 0.0f) : 0.0f;
-                *reinterpret_cast<uint2*>(sa2 + pr * kPS2 + m * 16 + kq * 4) =
-                    make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+                    bf16x8, *reinterpret_cast<const u32x4*>(bp + ((t / 3) * kA2W + t % 3) * kPS));
+                accs[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, b, accs[u], 0, 0, 0);
             }
         }
-    }
-    __syncthreads();
-
-    // ---- LDS bins for the decoded labels (over the first layer's region)
-    const int S = g.S;
-    const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
-    const int gx_hi = (min(x0 + kFW, g.w) - 1) / S + 1;
-    const int gy_hi = (min(y0 + kFH, g.h) - 1) / S + 1;
-    const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
-    unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
-    int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
-    for (int i = threadIdx.x; i < ncells; i += 256) {
-        const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
-        for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
-        const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
-        const int k = in_grid ? cy * g.ns_c + cx : -1;
-        kidx[i] = k;
-        if (in_grid && (cx * S) / kFW == static_cast<int>(blockIdx.x) &&
-            (cy * S) / kFH == static_cast<int>(blockIdx.y)) {
-            long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
-            for (int j = 0; j < kSumStride; ++j) z[j] = 0;
-        }
-    }
-    __syncthreads();
-
-    // ---- third layer, phase bias, argmax, decode, accumulate
-    {
-        bf16x8 w3[9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
-            w3[t] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(wt.W3b + ((t * 16 + row) * kC + kq * 8)));
-        const float scale = static_cast<float>(1 << kQShift);
-        for (int nt = wave; nt < kON; nt += 4) {
-            const int p = nt * 16 + row;
+        for (int u = 0; u < kPer; ++u) {
+            const int p = (wave + 4 * u) * 16 + row;
             const int r = p / kFW, c = p % kFW;
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int q = (r + t / 3) * kA2W + c + t % 3;
-                const bf16x8 b = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const u32x4*>(sa2 + q * kPS2 + kq * 8));
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[t], b, acc, 0, 0, 0);
-            }
             const int x = x0 + c, y = y0 + r;
-            const int ph = (y % S) * S + x % S;
             // this lane's classes 4 kq .. 4 kq + 3: best value, lowest class on ties
             float bv = -__builtin_huge_valf();
             int bc = 15;
@@ -717,7 +815,7 @@ __global__ __launch_bounds__(256) void net_fused_kernel(FusedImage g, NetWeights
             for (int i = 0; i < 4; ++i) {
                 const int o = kq * 4 + i;
                 if (o < kC3) {
-                    const float v = acc[i] + g.b3[o] + g.P[ph * kC3 + o];
+                    const float v = accs[u][i] + pb[u][i];
                     if (v > bv) {
                         bv = v;
                         bc = o;
@@ -734,37 +832,38 @@ __global__ __launch_bounds__(256) void net_fused_kernel(FusedImage g, NetWeights
                 }
             }
             if (kq == 0 && x < g.w && y < g.h) {
-                const int cy = min(max(y / S + bc / 3 - 1, 0), g.ns_r - 1);
-                const int cx = min(max(x / S + bc % 3 - 1, 0), g.ns_c - 1);
+                const int cy = min(max(tab[2 * kFW + r] + bc / 3 - 1, 0), g.ns_r - 1);
+                const int cx = min(max(tab[c] + bc % 3 - 1, 0), g.ns_c - 1);
                 const size_t pi = static_cast<size_t>(y) * g.w + x;
                 g.labels[pi] = cy * g.ns_c + cx;
                 const int cell = (cy - gy_lo) * ncx + (cx - gx_lo);
+                const float* lab = slab + p * 3;
                 atomicAdd(bins + cell, static_cast<unsigned long long>(
-                                           static_cast<long long>(rintf(g.L[pi] * scale))));
+                                           static_cast<long long>(rintf(lab[0] * scale))));
                 atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(
-                                                    static_cast<long long>(rintf(g.A[pi] * scale))));
+                                                    static_cast<long long>(rintf(lab[1] * scale))));
                 atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(
-                                                        static_cast<long long>(rintf(g.B[pi] * scale))));
+                                                        static_cast<long long>(rintf(lab[2] * scale))));
                 atomicAdd(bins + 3 * ncells + cell,
                           static_cast<unsigned long long>(c) |
                               (static_cast<unsigned long long>(r) << 20) | (1ull << 40));
             }
         }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < ncells; i += 256) {
-        const unsigned long long p = bins[3 * ncells + i];
-        const long long cnt = static_cast<long long>(p >> 40);
-        if (cnt == 0) continue;
-        unsigned long long* s =
-            reinterpret_cast<unsigned long long*>(g.sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
-        atomicAdd(s + 0, bins[i]);
-        atomicAdd(s + 1, bins[ncells + i]);
-        atomicAdd(s + 2, bins[2 * ncells + i]);
-        atomicAdd(s + 3, static_cast<unsigned long long>(static_cast<long long>(p & 0xFFFFFull) + cnt * x0));
-        atomicAdd(s + 4,
-                  static_cast<unsigned long long>(static_cast<long long>((p >> 20) & 0xFFFFFull) + cnt * y0));
-        atomicAdd(s + 5, static_cast<unsigned long long>(cnt));
+        __syncthreads();
+        for (int i = threadIdx.x; i < ncells; i += 256) {
+            const unsigned long long pk = bins[3 * ncells + i];
+            const long long cnt = static_cast<long long>(pk >> 40);
+            if (cnt == 0) continue;
+            unsigned long long* sm = reinterpret_cast<unsigned long long*>(
+                g.sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
+            atomicAdd(sm + 0, bins[i]);
+            atomicAdd(sm + 1, bins[ncells + i]);
+            atomicAdd(sm + 2, bins[2 * ncells + i]);
+            atomicAdd(sm + 3, static_cast<unsigned long long>(static_cast<long long>(pk & 0xFFFFFull) + cnt * x0));
+            atomicAdd(sm + 4, static_cast<unsigned long long>(
+                                  static_cast<long long>((pk >> 20) & 0xFFFFFull) + cnt * y0));
+            atomicAdd(sm + 5, static_cast<unsigned long long>(cnt));
+        }
     }
 }
 
@@ -805,7 +904,6 @@ size_t net_layout(int n, int cw, int ch, int S, int mode, NetWs* nw, char* base)
     w.wt.W3b = reinterpret_cast<unsigned short*>(take(9 * 16 * kC * 2));
     w.wt.W2t = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
     w.wt.W3t = reinterpret_cast<unsigned short*>(take(9 * kC * kC * 2));
-    w.wt.W1i = reinterpret_cast<unsigned short*>(take(kC * kC * 2));
     if (mode >= kForward) {
         w.x = reinterpret_cast<unsigned short*>(take(P * kC * 2));
         w.a1 = reinterpret_cast<unsigned short*>(take(P * kC * 2));
@@ -870,7 +968,7 @@ hipError_t enqueue_forward(const NetWs& nw, const CropTable& ct, int n, int cw, 
                            const float* params, hipStream_t s) {
     {
         KernelTimer t("net_prepare", s);
-        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt);
+        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt, 0, nullptr);
     }
     const int per = cw * ch;
     {
@@ -960,33 +1058,71 @@ hipError_t enqueue_backward(const NetWs& nw, const CropTable& ct, int n, int cw,
 
 }  // namespace
 
-size_t warm_net_bytes(int32_t w, int32_t h, int32_t S) {
-    if (!shape_ok(1, w, h, S)) return 0;
-    return net_layout(1, w, h, S, kWeights, nullptr, nullptr);
+// A prepared net: the bf16 weight copies followed by the FP32 parameter
+// vector, sized for the largest S so that a phase index never leaves it.
+constexpr int kMaxParams = kOffP + kC3 * kMaxS * kMaxS;
+
+size_t prepared_layout(NetWeights* wt, float** params, char* base) {
+    NetWs nw;
+    const size_t off = net_layout(1, 1, 1, 1, kWeights, &nw, base);
+    if (wt) *wt = nw.wt;
+    if (params) *params = base ? reinterpret_cast<float*>(base + off) : nullptr;
+    return off + align_up(static_cast<size_t>(kMaxParams) * sizeof(float));
 }
 
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
-                             const float* params, void* net_ws, hipStream_t s) {
-    NetWs nw;
-    net_layout(1, w, h, g.S, kWeights, &nw, static_cast<char*>(net_ws));
-    {
-        KernelTimer t("net_prepare", s);
-        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt);
-    }
+                             const void* d_net, hipStream_t s) {
+    NetWeights wt;
+    float* params;
+    prepared_layout(&wt, &params, static_cast<char*>(const_cast<void*>(d_net)));
     const size_t ring = static_cast<size_t>(g.K) * kSumStride;
+    const int tiles_x = (w + kFW - 1) / kFW;
+    const int n_tiles = tiles_x * ((h + kFH - 1) / kFH);
     FusedImage f{ws.L, ws.A, ws.B, w, h, g.S, g.ns_c, g.ns_r,
                  params + kOffB1, params + kOffB2, params + kOffB3, params + kOffP,
-                 ws.labels, ws.sums, ws.sums + ring};
+                 ws.labels, ws.sums, ws.sums + ring, tiles_x, n_tiles};
+    // persistent workgroups: two per compute unit (their LDS fits twice)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const int grid = n_tiles < 2 * cus ? n_tiles : 2 * cus;
+    static bool lds_set = false;  // above 64 KiB of dynamic LDS needs the opt-in
+    if (!lds_set) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(net_fused_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(kFusedLds));
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
     KernelTimer t("net_fused", s);
-    net_fused_kernel<<<dim3((w + kFW - 1) / kFW, (h + kFH - 1) / kFH), 256, kFusedLds, s>>>(f, nw.wt);
+    net_fused_kernel<<<grid, 256, kFusedLds, s>>>(f, wt);
     return hipGetLastError();
 }
+
+bool warm_supported(int32_t S) { return S >= 1 && S <= kMaxS; }
 
 }  // namespace slic
 
 using namespace slic;
 
 extern "C" {
+
+size_t slic_net_prepared_bytes(void) { return prepared_layout(nullptr, nullptr, nullptr); }
+
+int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_stream) {
+    if (S < 1 || S > kMaxS || !device_ptr(d_params) || !device_ptr(d_net) ||
+        reinterpret_cast<uintptr_t>(d_net) % kAlign != 0)
+        return SLIC_EINVAL;
+    NetWeights wt;
+    float* params;
+    prepared_layout(&wt, &params, static_cast<char*>(d_net));
+    const int count = kOffP + kC3 * S * S;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int n = count > 9 * kC * kC ? count : 9 * kC * kC;
+    prepare_kernel<<<(n + 255) / 256, 256, 0, s>>>(d_params, wt, count, params);
+    return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
+}
 
 int32_t slic_net_param_count(int32_t S) {
     if (S < 1 || S > kMaxS) return 0;

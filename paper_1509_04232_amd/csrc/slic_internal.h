@@ -131,15 +131,14 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
 hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out, int32_t* counts,
                                  hipStream_t s);
 
-// Learned warm start (net.hip).  warm_net_bytes: the net's forward
-// buffers for one w x h image at step S (0 if unsupported).
-// launch_warm_start: after launch_lab_seed, runs the net on ws.L/A/B,
-// writes the decoded labels to ws.labels, accumulates them into the first
-// accumulator buffer (as association launch 0 would) and clears the second,
-// so that association launch 1 starts from the net's labels.
-size_t warm_net_bytes(int32_t w, int32_t h, int32_t S);
+// Learned warm start (net.hip).  warm_supported: the net handles step S.
+// launch_warm_start: after launch_lab_seed, runs the prepared net d_net on
+// ws.L/A/B, writes the decoded labels to ws.labels, accumulates them into
+// the first accumulator buffer (as association launch 0 would) and clears
+// the second, so that association launch 1 starts from the net's labels.
+bool warm_supported(int32_t S);
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
-                             const float* params, void* net_ws, hipStream_t s);
+                             const void* d_net, hipStream_t s);
 
 // Kernel timing: while enabled, a KernelTimer brackets a launch with HIP
 // events on the launch stream.

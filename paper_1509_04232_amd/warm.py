@@ -125,12 +125,26 @@ class Net:
         return loss
 
 
-def warm_segment(rgb: torch.Tensor, p, net_params: torch.Tensor, iters: int,
+def prepare(params: torch.Tensor, S: int, stream=None, out: torch.Tensor | None = None):
+    """slic_net_prepare: the inference copy of a parameter vector (a uint8
+    device tensor of slic_net_prepared_bytes())."""
+    if params.dtype != torch.float32 or params.device.type != "cuda":
+        raise ValueError("params must be a float32 GPU tensor")
+    if params.numel() != _abi.slic_net_param_count(S):
+        raise ValueError(f"expected {_abi.slic_net_param_count(S)} parameters for S={S}")
+    net = out if out is not None else torch.empty(_abi.slic_net_prepared_bytes(),
+                                                  dtype=torch.uint8, device=params.device)
+    _abi.slic_net_prepare(S, params.data_ptr(), net.data_ptr(), _stream(stream))
+    return net
+
+
+def warm_segment(rgb: torch.Tensor, p, net: torch.Tensor, iters: int,
                  enforce: bool = False, want_centres: bool = False, want_energy: bool = True,
                  stream=None, workspace=None) -> dict:
-    """slic_warm_segment: the net's labels as the first association, then
-    ``iters`` rounds of (update, associate).  Returns device tensors: labels,
-    and optionally centres, energy, n_segments."""
+    """slic_warm_segment: the prepared net's labels (``prepare``) as the
+    first association, then ``iters`` rounds of (update, associate).
+    Returns device tensors: labels, and optionally centres, energy,
+    n_segments."""
     from . import _check_rgb
     _check_rgb(rgb, p)
     cp = p.c()
@@ -145,7 +159,7 @@ def warm_segment(rgb: torch.Tensor, p, net_params: torch.Tensor, iters: int,
     if enforce:
         out["n_segments"] = torch.empty(1, dtype=torch.int32, device=dev)
     ptr = lambda k: out[k].data_ptr() if k in out else None  # noqa: E731
-    _abi.slic_warm_segment(cp, rgb.data_ptr(), net_params.data_ptr(), iters, 1 if enforce else 0,
+    _abi.slic_warm_segment(cp, rgb.data_ptr(), net.data_ptr(), iters, 1 if enforce else 0,
                            out["labels"].data_ptr(), ptr("centres"), ptr("energy"),
                            ptr("n_segments"), _stream(stream), ws.data_ptr(), ws.numel())
     return out

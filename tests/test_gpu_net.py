@@ -197,7 +197,8 @@ def test_warm_segment_matches_oracle(slic, w, h, S, perturb, iters):
     energy = oracle.energy(lab, S, 10.0, cen, labels)
 
     prm = slic.Params(w, h, S=S, m=10.0, perturb=perturb)
-    out = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, _dev(p), iters, want_centres=True)
+    net = slic.warm.prepare(_dev(p), S)
+    out = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, net, iters, want_centres=True)
     torch.cuda.synchronize()
     assert np.array_equal(out["labels"].cpu().numpy(), labels)
     assert np.array_equal(out["centres"].cpu().numpy(), cen)
@@ -217,7 +218,8 @@ def test_fused_decode_matches_oracle_away_from_ties(slic, w, h, S, seed):
     top = np.take_along_axis(lg, order[..., :2], axis=-1)
     margin = top[..., 0] - top[..., 1]
     prm = slic.Params(w, h, S=S, m=10.0)
-    got = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, _dev(p), 0)["labels"].cpu().numpy()
+    net = slic.warm.prepare(_dev(p), S)
+    got = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, net, 0)["labels"].cpu().numpy()
     want = oracle.net_decode(lg, S)
     clear = margin > 0.02 * np.abs(lg).max()
     assert clear.mean() > 0.8
@@ -231,11 +233,11 @@ def test_fused_decode_matches_oracle_away_from_ties(slic, w, h, S, seed):
 def test_warm_context_resumes_and_enforces(slic):
     w, h, S = 120, 80, 8
     img, lab = _image(w, h, 61)
-    p = _dev(_decisive_params(S, 62))
+    p = slic.warm.prepare(_dev(_decisive_params(S, 62)), S)
     prm = slic.Params(w, h, S=S, m=10.0)
     rgb = _dev(img.reshape(-1))
     one = slic.warm.warm_segment(rgb, prm, p, 3, enforce=True)
-    ctx = slic.Context(prm, rgb, net_params=p)
+    ctx = slic.Context(prm, rgb, net=p)
     ctx.iterate(1).iterate(2)
     split = ctx.labels()
     n = ctx.enforce_connectivity()
@@ -271,5 +273,10 @@ def test_net_rejects_bad_arguments(slic):
         _abi.slic_warm_workspace_bytes(slic.Params(200, 200, S=40).c())
     prm = slic.Params(40, 30, S=8)
     rgb = _dev(img.reshape(-1))
-    with pytest.raises(_abi.SlicError):  # parameters in host memory
-        slic.warm.warm_segment(rgb, prm, torch.zeros(net.count), 2)
+    with pytest.raises(_abi.SlicError):  # prepared net in host memory
+        slic.warm.warm_segment(rgb, prm, torch.zeros(_abi.slic_net_prepared_bytes(),
+                                                     dtype=torch.uint8), 2)
+    with pytest.raises(_abi.SlicError):  # S beyond the phase table
+        _abi.slic_net_prepare(33, net.params.data_ptr(), net.ws.data_ptr(), 0)
+    with pytest.raises(ValueError):  # parameter count of another S
+        slic.warm.prepare(net.params, 16)

@@ -81,8 +81,10 @@ def test_training_improves_the_warm_start(slic, trained):
         wl = warm_eval_workload(j)
         rgb = _rgb(wl)
         p = slic.Params(wl.width, wl.height, S=S, m=wl.m)
-        e_t = float(slic.warm.warm_segment(rgb, p, net.params, 2)["energy"].cpu()[0])
-        e_u = float(slic.warm.warm_segment(rgb, p, untrained, 2)["energy"].cpu()[0])
+        trained_net = slic.warm.prepare(net.params, S)
+        untrained_net = slic.warm.prepare(untrained, S)
+        e_t = float(slic.warm.warm_segment(rgb, p, trained_net, 2)["energy"].cpu()[0])
+        e_u = float(slic.warm.warm_segment(rgb, p, untrained_net, 2)["energy"].cpu()[0])
         assert e_t < e_u, (e_t, e_u)
 
 
@@ -92,7 +94,7 @@ def test_gate_falls_back_to_plain(slic, trained):
     rgb = _rgb(wl)
     p = slic.Params(wl.width, wl.height, S=S, m=wl.m)
     plain = slic.segment(rgb, p, 10, want_energy=True)
-    warm = slic.warm.warm_segment(rgb, p, net.params, 2)
+    warm = slic.warm.warm_segment(rgb, p, slic.warm.prepare(net.params, S), 2)
     ep, ew = float(plain["energy"].cpu()[0]), float(warm["energy"].cpu()[0])
     out = warm if slic.warm.passes_gate(ew, ep) else plain
     e = float(out["energy"].cpu()[0])
