@@ -54,6 +54,7 @@ def _load():
         "orc_kmeans": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _P, _P, _P],
         "orc_kmeans_converge": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _F, _P, _P, _P, _P],
         "orc_residual": [_P, _P, _I],
+        "orc_stray_filter": [_P, _I, _I, _I, _P],
         "orc_energy": [_P, _P, _P, _I, _I, _I, _F, _P, _I, _P, _P],
         "orc_connectivity": [_P, _I, _I, _I, _I, _P, _P, _P],
         "orc_lab_tables": [_P, _P],
@@ -215,6 +216,15 @@ def residual(prev: np.ndarray, nxt: np.ndarray) -> int:
     a = np.ascontiguousarray(prev, np.float32)
     b = np.ascontiguousarray(nxt, np.float32)
     return int(_load().orc_residual(_ptr(a), _ptr(b), a.shape[0]))
+
+
+def stray_filter(labels: np.ndarray, passes: int = 2) -> np.ndarray:
+    """Section 3's stray-pixel filter, `passes` passes (the paper runs two)."""
+    lb = np.ascontiguousarray(labels, np.int32)
+    h, w = lb.shape
+    out = np.empty_like(lb)
+    _check(_load().orc_stray_filter(_ptr(lb), w, h, passes, _ptr(out)), "stray_filter")
+    return out
 
 
 def energy(lab, S: int, m: float, centres: np.ndarray, labels: np.ndarray) -> float:

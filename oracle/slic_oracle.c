@@ -517,3 +517,52 @@ int orc_connectivity(const int32_t* labels, int32_t w, int32_t h, int32_t S, int
     free(comp); free(size); free(stack); free(join); free(rank);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Stray-pixel filter (Section 3, "Enforce connectivity": two one-thread-
+ * per-pixel calls of one kernel; a pixel takes the label of the surrounding
+ * pixels when all of them carry a different label).
+ * READING: the surrounding pixels are the 4-connected neighbours inside the
+ * image (up, left, right, down).  A pixel none of whose neighbours shares its
+ * label takes the label that occurs most often among them, ties going to the
+ * first in the order up, left, right, down; every pixel decides from the
+ * input of the pass (a pass reads one map and writes another).  `passes`
+ * passes; in and out may not overlap.
+ * ---------------------------------------------------------------------- */
+static int32_t orc_stray_pixel(const int32_t* in, int32_t w, int32_t h, int32_t x, int32_t y) {
+    const int32_t own = in[(size_t)y * w + x];
+    int32_t nb[4];
+    int n = 0;
+    if (y > 0) nb[n++] = in[(size_t)(y - 1) * w + x];
+    if (x > 0) nb[n++] = in[(size_t)y * w + x - 1];
+    if (x + 1 < w) nb[n++] = in[(size_t)y * w + x + 1];
+    if (y + 1 < h) nb[n++] = in[(size_t)(y + 1) * w + x];
+    if (n == 0) return own;
+    for (int i = 0; i < n; i++)
+        if (nb[i] == own) return own;
+    int best = 0, best_count = 0;
+    for (int i = 0; i < n; i++) {
+        int count = 0;
+        for (int j = 0; j < n; j++) count += nb[j] == nb[i];
+        if (count > best_count) {  /* strictly more: ties keep the earlier */
+            best_count = count;
+            best = i;
+        }
+    }
+    return nb[best];
+}
+
+int orc_stray_filter(const int32_t* in, int32_t w, int32_t h, int32_t passes, int32_t* out) {
+    if (!in || !out || w < 1 || h < 1 || passes < 0) return ORC_EINVAL;
+    size_t n = (size_t)w * h;
+    int32_t* tmp = malloc(sizeof(int32_t) * n);
+    if (!tmp) return ORC_ENOMEM;
+    memcpy(out, in, sizeof(int32_t) * n);
+    for (int32_t p = 0; p < passes; p++) {
+        memcpy(tmp, out, sizeof(int32_t) * n);
+        for (int32_t y = 0; y < h; y++)
+            for (int32_t x = 0; x < w; x++) out[(size_t)y * w + x] = orc_stray_pixel(tmp, w, h, x, y);
+    }
+    free(tmp);
+    return ORC_OK;
+}
