@@ -304,6 +304,76 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
             "label_agreement_mean": round(float(np.mean(agree)), 4)}
 
 
+def bench_video(slic, torch, dev, n_frames: int, rounds: int, reps: int):
+    """Row f3, the video warm start: a shaking hand-held camera (c2-sized
+    frames, S=16, m=10).  Plain: every frame from seeds, 10 rounds.  Warm:
+    the first frame plain, every later frame from the previous frame's
+    centres with `rounds` rounds.  Frames/s of both chains, and each warm
+    frame's energy against plain 10-round energy of the same frame."""
+    import numpy as np
+
+    import synth
+    from synth.configs import video_workload
+    canvas, origins = video_workload(n_frames)
+    img = synth.image_for(canvas)
+    frames = [torch.from_numpy(np.ascontiguousarray(img[oy:oy + 480, ox:ox + 640]).reshape(-1)).to(dev)
+              for ox, oy in origins]
+    p = slic.Params(640, 480, S=16, m=10.0)
+    cp = p.c()
+    K = p.n_clusters
+    stream = torch.cuda.current_stream().cuda_stream
+    ws = slic.workspace_for(p, dev)
+    labels = torch.empty((480, 640), dtype=torch.int32, device=dev)
+    cen = [torch.empty((K, 5), dtype=torch.float32, device=dev) for _ in range(2)]
+    e_plain = torch.empty(n_frames, dtype=torch.float64, device=dev)
+    e_warm = torch.empty(n_frames, dtype=torch.float64, device=dev)
+
+    def plain(with_energy):
+        for i, f in enumerate(frames):
+            slic.slic_segment(cp, f.data_ptr(), 10, 0, labels.data_ptr(), None,
+                              e_plain[i:].data_ptr() if with_energy else None, None, stream,
+                              ws.data_ptr(), ws.numel())
+
+    def warm(with_energy):
+        for i, f in enumerate(frames):
+            if i == 0:
+                ctx = slic.slic_init(cp, f.data_ptr(), stream, ws.data_ptr(), ws.numel())
+                slic.slic_iterate(ctx, 10)
+            else:
+                ctx = slic.slic_init_from_centres(cp, f.data_ptr(), cen[(i - 1) % 2].data_ptr(),
+                                                  stream, ws.data_ptr(), ws.numel())
+                slic.slic_iterate(ctx, rounds)
+            if with_energy:
+                slic.slic_energy(ctx, e_warm[i:].data_ptr())
+            slic.slic_get_centres(ctx, cen[i % 2].data_ptr(), None)
+            slic.slic_get_labels(ctx, labels.data_ptr())
+            slic.slic_destroy(ctx)
+
+    def timed(fn):
+        fn(False)
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn(False)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t)
+        runs.sort()
+        return runs[len(runs) // 2]
+
+    t_plain, t_warm = timed(plain), timed(warm)
+    plain(True)
+    warm(True)
+    torch.cuda.synchronize()
+    ratio = (e_warm.cpu().numpy() / e_plain.cpu().numpy())[1:]
+    return {"frames": n_frames, "size": "640x480", "S": 16, "warm_rounds": rounds,
+            "plain_frames_per_s": round(n_frames / t_plain, 1),
+            "warm_frames_per_s": round(n_frames / t_warm, 1),
+            "energy_ratio_mean": round(float(ratio.mean()), 4),
+            "energy_ratio_max": round(float(ratio.max()), 4),
+            "frames_within_1pct": int((ratio <= 1.01).sum())}
+
+
 def traffic_from_profile():
     """HBM bytes per association launch from the committed PMC summary, or
     None if it is missing or the kernel source changed since."""
@@ -445,6 +515,7 @@ def main() -> int:
         extra["c4"] = bench_c4(slic, torch, dev, reps=max(5, args.steps // 50))
         extra["c5"] = bench_c5(slic, torch, dev, args.train_steps, args.train_images, 32,
                                reps=max(3, args.steps // 100))
+        extra["video"] = bench_video(slic, torch, dev, 32, 2, reps=max(3, args.steps // 100))
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -85,6 +85,15 @@ int slic_grid(const slic_params* p, int32_t* S, int32_t* ns_c, int32_t* ns_r);
 int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* hip_stream,
               void* d_ws, size_t ws_bytes);
 
+/* Video warm start (the paper's use case is a live camera stream): like
+ * slic_init, but the centres are d_centres (device float[K][5], (L, a, b,
+ * x, y), finite; typically the previous frame's slic_get_centres with the
+ * same parameters) instead of seeds, so a few rounds reach the energy that
+ * seeding needs many for.  d_centres may be reused once the call's work has
+ * completed on the stream. */
+int slic_init_from_centres(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                           const float* d_centres, void* hip_stream, void* d_ws, size_t ws_bytes);
+
 /* n_iters >= 0 rounds of (update every centre to the mean of its pixels;
  * associate every pixel), the loop body of Section 4's listing.
  * slic_iterate(c, a) followed by slic_iterate(c, b) equals
@@ -112,6 +121,17 @@ int slic_iterate_converge(slic_ctx* ctx, int32_t max_iters, float threshold,
  * be NULL) receives their count.  Afterwards slic_iterate and slic_energy
  * return SLIC_ESTATE; the centres stay those of the last association. */
 int slic_enforce_connectivity(slic_ctx* ctx, int32_t* d_n_segments);
+
+/* The paper's own clean-up (Section 3, "Enforce connectivity"), a cheaper
+ * alternative to slic_enforce_connectivity that does not guarantee
+ * connected segments: `passes` (>= 0; the paper uses 2) one-thread-per-pixel
+ * passes in which a pixel none of whose 4-neighbours inside the image shares
+ * its label takes the label that occurs most often among them (ties: the
+ * first in the order up, left, right, down); each pass reads the map the
+ * previous one wrote.  Relabels the context's label map in place; labels stay
+ * cluster indices.  Afterwards slic_iterate and slic_energy return
+ * SLIC_ESTATE. */
+int slic_filter_stray(slic_ctx* ctx, int32_t passes);
 
 /* Copies of the context's state (device to device, on the context's
  * stream).  Labels: int32[height*width], row-major.  Centres: float[K][5]

@@ -15,9 +15,10 @@ from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, S
                    SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_assign_variant_info,
                    slic_assign_variants, slic_autotune, slic_batch_autotune, slic_batch_create,
                    slic_batch_destroy, slic_batch_run, slic_batch_workspace_bytes,
-                   slic_destroy, slic_segment_batch,
+                   slic_destroy, slic_filter_stray, slic_segment_batch,
                    slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
                    slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
+                   slic_init_from_centres,
                    slic_iterate, slic_iterate_converge, slic_segment, slic_set_assign_variant,
                    slic_strerror,
                    slic_timing_enable, slic_timing_read, slic_workspace_bytes,
@@ -84,13 +85,20 @@ class Context:
     net, ``warm.prepare``, is given), then iterate / enforce / get."""
 
     def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None,
-                 net: torch.Tensor | None = None):
+                 net: torch.Tensor | None = None, centres: torch.Tensor | None = None):
         _check_rgb(rgb, p)
         self.params = p
         self._cp = p.c()
         self.stream = stream
         self._rgb = rgb  # kept alive until the conversion has run
-        if net is None:
+        if centres is not None:  # video warm start from a previous frame's centres
+            if centres.dtype != torch.float32 or tuple(centres.shape) != (p.n_clusters, 5) or \
+                    not centres.is_contiguous():
+                raise ValueError("centres must be a contiguous float32 (K, 5) tensor")
+            self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
+            self.ctx = slic_init_from_centres(self._cp, rgb.data_ptr(), centres.data_ptr(),
+                                              _stream(stream), self.ws.data_ptr(), self.ws.numel())
+        elif net is None:
             self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
             self.ctx = slic_init(self._cp, rgb.data_ptr(), _stream(stream), self.ws.data_ptr(),
                                  self.ws.numel())
@@ -116,6 +124,11 @@ class Context:
         n = torch.empty(1, dtype=torch.int32, device=self.device)
         slic_enforce_connectivity(self.ctx, n.data_ptr())
         return n
+
+    def filter_stray(self, passes: int = 2) -> "Context":
+        """Section 3's stray-pixel filter (the paper's two passes by default)."""
+        slic_filter_stray(self.ctx, passes)
+        return self
 
     def labels(self) -> torch.Tensor:
         out = torch.empty((self.params.height, self.params.width), dtype=torch.int32,

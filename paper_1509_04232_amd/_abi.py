@@ -53,9 +53,12 @@ _SIGS = {
     "slic_workspace_bytes": ([_PP], ctypes.c_size_t),
     "slic_grid": ([_PP, _P, _P, _P], ctypes.c_int),
     "slic_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_init_from_centres": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t],
+                               ctypes.c_int),
     "slic_iterate": ([_P, _I], ctypes.c_int),
     "slic_iterate_converge": ([_P, _I, ctypes.c_float, _P], ctypes.c_int),
     "slic_enforce_connectivity": ([_P, _P], ctypes.c_int),
+    "slic_filter_stray": ([_P, _I], ctypes.c_int),
     "slic_get_labels": ([_P, _P], ctypes.c_int),
     "slic_get_centres": ([_P, _P, _P], ctypes.c_int),
     "slic_get_lab": ([_P, _P, _P, _P], ctypes.c_int),
@@ -125,6 +128,14 @@ def slic_init(p: SlicParams, d_rgb: int, stream: int, d_ws: int, ws_bytes: int) 
     return int(ctx.value)
 
 
+def slic_init_from_centres(p: SlicParams, d_rgb: int, d_centres: int, stream: int, d_ws: int,
+                           ws_bytes: int) -> int:
+    ctx = _P()
+    _check(lib.slic_init_from_centres(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_centres, stream,
+                                      d_ws, ws_bytes), "slic_init_from_centres")
+    return int(ctx.value)
+
+
 def slic_iterate(ctx: int, n_iters: int) -> None:
     _check(lib.slic_iterate(ctx, n_iters), "slic_iterate")
 
@@ -137,6 +148,10 @@ def slic_iterate_converge(ctx: int, max_iters: int, threshold: float,
 
 def slic_enforce_connectivity(ctx: int, d_n_segments: int | None) -> None:
     _check(lib.slic_enforce_connectivity(ctx, d_n_segments), "slic_enforce_connectivity")
+
+
+def slic_filter_stray(ctx: int, passes: int) -> None:
+    _check(lib.slic_filter_stray(ctx, passes), "slic_filter_stray")
 
 
 def slic_get_labels(ctx: int, d_labels: int) -> None:

@@ -429,6 +429,38 @@ int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* 
     return SLIC_OK;
 }
 
+int slic_init_from_centres(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                           const float* d_centres, void* hip_stream, void* d_ws, size_t ws_bytes) {
+    if (!out || !params_ok(p) || !d_rgb || !d_centres || !d_ws || !aligned(d_ws))
+        return SLIC_EINVAL;
+    *out = nullptr;
+    if (ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc == SLIC_OK) rc = check_device_ptr(d_centres);
+    if (rc) return rc;
+    slic_ctx* c = new (std::nothrow) slic_ctx;
+    if (!c) return SLIC_ENOMEM;
+    bind(c, p, d_ws, hip_stream);
+    const slic_params& q = c->p;
+    // the conversion kernel also seeds (and clears the counts and first
+    // accumulators); the given centres then replace the seeds
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess)
+        e = launch_lab_seed(d_rgb, q.width, q.height, q.pitch, q.channels, c->ws, c->g, 0, c->stream);
+    if (e == hipSuccess) e = launch_import_centres(c->ws, c->g, d_centres, c->stream);
+    if (e == hipSuccess) {
+        c->t = 0;
+        e = launch_assign(c->ws, q.width, q.height, c->g, c->t, c->variant, c->stream);
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return SLIC_EHIP;
+    }
+    c->t = 1;
+    *out = c;
+    return SLIC_OK;
+}
+
 int slic_iterate(slic_ctx* c, int32_t n_iters) {
     if (!c || n_iters < 0) return SLIC_EINVAL;
     if (c->state != 0) return SLIC_ESTATE;
@@ -463,6 +495,16 @@ int slic_enforce_connectivity(slic_ctx* c, int32_t* d_n_segments) {
     if (c->state != 0 && c->state != 3) return SLIC_ESTATE;
     if (launch_connectivity(c->ws, c->p.width, c->p.height, c->g, c->p.min_segment, c->ws.labels,
                             d_n_segments, c->stream) != hipSuccess)
+        return fail(c);
+    c->state = 1;
+    return SLIC_OK;
+}
+
+int slic_filter_stray(slic_ctx* c, int32_t passes) {
+    if (!c || passes < 0) return SLIC_EINVAL;
+    if (c->state != 0 && c->state != 3) return SLIC_ESTATE;
+    if (launch_stray_filter(c->ws, c->p.width, c->p.height, c->ws.labels, passes, c->stream) !=
+        hipSuccess)
         return fail(c);
     c->state = 1;
     return SLIC_OK;

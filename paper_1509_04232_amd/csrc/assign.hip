@@ -435,6 +435,14 @@ __global__ __launch_bounds__(256) void export_centres_kernel(int K, const float*
     if (out_counts) out_counts[k] = counts[k];
 }
 
+__global__ __launch_bounds__(256) void import_centres_kernel(int K, const float* __restrict__ in,
+                                                             float* __restrict__ cen) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    for (int j = 0; j < 5; ++j)
+        cen[static_cast<size_t>(k) * kCenStride + j] = in[5 * static_cast<size_t>(k) + j];
+}
+
 template <int VEC, int ROWS>
 size_t variant_lds(int S) {
     using Sh = Shape<VEC, ROWS>;
@@ -584,6 +592,13 @@ hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out,
                                  hipStream_t s) {
     KernelTimer t("export_centres", s);
     export_centres_kernel<<<(g.K + 255) / 256, 256, 0, s>>>(g.K, ws.cen, ws.counts, out, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_centres(const Workspace& ws, const Grid& g, const float* in,
+                                 hipStream_t s) {
+    KernelTimer t("import_centres", s);
+    import_centres_kernel<<<(g.K + 255) / 256, 256, 0, s>>>(g.K, in, ws.cen);
     return hipGetLastError();
 }
 

@@ -326,4 +326,67 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
     return hipSuccess;
 }
 
+// Stray-pixel filter (Section 3's clean-up: two one-thread-per-pixel passes
+// of one kernel).  A pixel none of whose 4-neighbours inside the image shares
+// its label takes the label that occurs most often among them, ties going to
+// the first in the order up, left, right, down.  Each pass reads one map and
+// writes the other.
+namespace {
+
+__global__ __launch_bounds__(kBlock) void stray_kernel(const int32_t* __restrict__ in, int w, int h,
+                                                       int32_t* __restrict__ out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= w * h) return;
+    const int x = i % w, y = i / w;
+    const int32_t own = in[i];
+    int32_t nb[4];
+    int n = 0;
+    if (y > 0) nb[n++] = in[i - w];
+    if (x > 0) nb[n++] = in[i - 1];
+    if (x + 1 < w) nb[n++] = in[i + 1];
+    if (y + 1 < h) nb[n++] = in[i + w];
+    bool stray = n > 0;
+    for (int j = 0; j < n; ++j) stray = stray && nb[j] != own;
+    int32_t v = own;
+    if (stray) {
+        int best_count = 0;
+        for (int j = 0; j < n; ++j) {
+            int count = 0;
+            for (int k = 0; k < n; ++k) count += nb[k] == nb[j];
+            if (count > best_count) {
+                best_count = count;
+                v = nb[j];
+            }
+        }
+    }
+    out[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void copy_labels_kernel(const int32_t* __restrict__ in, int n,
+                                                             int32_t* __restrict__ out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+}  // namespace
+
+hipError_t launch_stray_filter(const Workspace& ws, int32_t w, int32_t h, int32_t* labels,
+                               int32_t passes, hipStream_t s) {
+    const int n = w * h;
+    const int nb = (n + kBlock - 1) / kBlock;
+    int32_t* buf[2] = {labels, ws.ccl0};
+    for (int p = 0; p < passes; ++p) {
+        KernelTimer t("stray", s);
+        stray_kernel<<<nb, kBlock, 0, s>>>(buf[p & 1], w, h, buf[(p + 1) & 1]);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (passes & 1) {
+        KernelTimer t("stray_copy", s);
+        copy_labels_kernel<<<nb, kBlock, 0, s>>>(ws.ccl0, n, labels);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
 }  // namespace slic

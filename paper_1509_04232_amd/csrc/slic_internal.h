@@ -128,6 +128,13 @@ hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& 
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
                                hipStream_t s);
+// Section 3's stray-pixel filter on `labels` in place (ws.ccl0 as the second
+// buffer), `passes` passes.
+hipError_t launch_stray_filter(const Workspace& ws, int32_t w, int32_t h, int32_t* labels,
+                               int32_t passes, hipStream_t s);
+// Centres float[K][5] from the caller into the workspace (stride kCenStride).
+hipError_t launch_import_centres(const Workspace& ws, const Grid& g, const float* in,
+                                 hipStream_t s);
 hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out, int32_t* counts,
                                  hipStream_t s);
 

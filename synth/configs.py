@@ -84,12 +84,18 @@ def image_for(wl: Workload):
     return voronoi_image(wl.seed, wl.width, wl.height, wl.regions, wl.sigma, wl.ramp)
 
 
-def video_workload(n_frames: int = 32, width: int = 640, height: int = 480, pan=(3, 2),
+def video_workload(n_frames: int = 32, width: int = 640, height: int = 480, shake: int = 2,
                    seed: int = 5_000_000):
-    """A panning camera over one seeded Voronoi canvas: frame t is the
-    width x height crop at (t * pan[0], t * pan[1]).  The canvas keeps c2's
-    region density.  Returns (canvas workload, [(x, y) origin per frame])."""
-    cw, ch = width + pan[0] * (n_frames - 1), height + pan[1] * (n_frames - 1)
+    """A hand-held camera over one seeded Voronoi canvas: frame t is the
+    width x height crop at (shake + dx_t, shake + dy_t), with dx_t, dy_t in
+    [-shake, shake] drawn by SplitMix64 (key = seed), so the view shakes
+    around a fixed point.  The canvas keeps c2's region density.  Returns
+    (canvas workload, [(x, y) origin per frame])."""
+    cw, ch = width + 2 * shake, height + 2 * shake
     regions = max(1, round(256 * cw * ch / (640 * 480)))
     canvas = Workload(f"video[{seed}]", cw, ch, regions, 8.0, seed, 16)
-    return canvas, [(t * pan[0], t * pan[1]) for t in range(n_frames)]
+    origins = []
+    for t in range(n_frames):
+        r = _splitmix_at(seed, t)
+        origins.append((int(r % (2 * shake + 1)), int((r >> 16) % (2 * shake + 1))))
+    return canvas, origins
