@@ -52,6 +52,10 @@ def _load():
         "orc_assign": [_P, _P, _P, _I, _I, _I, _F, _P, _P],
         "orc_update": [_P, _P, _P, _I, _I, _P, _I, _P, _P],
         "orc_kmeans": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _P, _P, _P],
+        "orc_kmeans_ex": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _I, _P, _P, _P],
+        "orc_assign_ex": [_P, _P, _P, _I, _I, _I, _F, _I, _P, _P],
+        "orc_energy_ex": [_P, _P, _P, _I, _I, _I, _F, _I, _P, _I, _P, _P],
+        "orc_rgb_to_space": [_P, _I, _I, _I, _I, _I, _P, _P, _P],
         "orc_kmeans_converge": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _F, _P, _P, _P, _P],
         "orc_residual": [_P, _P, _I],
         "orc_stray_filter": [_P, _I, _I, _I, _P],
@@ -121,6 +125,21 @@ def lab_tables():
     return lin, nm.reshape(3, 3)
 
 
+COLOR_LAB, COLOR_XYZ, COLOR_RGB = 0, 1, 2
+DIST_EQ1, DIST_SQUARED = 0, 1
+
+
+def rgb_to_space(rgb: np.ndarray, space: int):
+    """The colour planes of another colour space (0 CIELAB, 1 XYZ x 100,
+    2 the R, G, B bytes as floats)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    h, w, c = rgb.shape
+    out = [np.empty((h, w), np.float32) for _ in range(3)]
+    _check(_load().orc_rgb_to_space(_ptr(rgb), w, h, w * c, c, space, *[_ptr(o) for o in out]),
+           "colour space")
+    return tuple(out)
+
+
 def rgb_to_lab(rgb: np.ndarray, pitch: int | None = None):
     """Section 3, image space conversion.  ``rgb``: uint8 (H, W, C), C in {3, 4},
     or a flat byte buffer with ``pitch``.  Returns planar float32 (L, a, b),
@@ -157,14 +176,15 @@ def weight(m: float, S: int) -> float:
     return float(_load().orc_weight(float(m), S))
 
 
-def assign(lab, S: int, m: float, centres: np.ndarray):
-    """Eq. 1 and Section 3's nine-candidate association.  Returns int32 (H, W)."""
+def assign(lab, S: int, m: float, centres: np.ndarray, dist: int = DIST_EQ1):
+    """Eq. 1 (or, with dist=1, the squared-sum distance) and Section 3's
+    nine-candidate association.  Returns int32 (H, W)."""
     L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
     h, w = L.shape
     cen = np.ascontiguousarray(centres, np.float32)
     lab_out = np.empty((h, w), np.int32)
-    _check(_load().orc_assign(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), _ptr(cen),
-                              _ptr(lab_out)), "assign")
+    _check(_load().orc_assign_ex(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(dist),
+                                 _ptr(cen), _ptr(lab_out)), "assign")
     return lab_out
 
 
@@ -180,7 +200,7 @@ def update(lab, labels: np.ndarray, centres: np.ndarray):
     return cen, cnt
 
 
-def kmeans(lab, S: int, m: float, perturb: bool, iters: int):
+def kmeans(lab, S: int, m: float, perturb: bool, iters: int, dist: int = DIST_EQ1):
     """Section 4's loop: seed, associate, iters x (update, associate).
     Returns (labels (H,W), centres (K,5), counts (K,))."""
     L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
@@ -189,8 +209,8 @@ def kmeans(lab, S: int, m: float, perturb: bool, iters: int):
     cen = np.empty((nc * nr, 5), np.float32)
     cnt = np.empty(nc * nr, np.int32)
     lb = np.empty((h, w), np.int32)
-    _check(_load().orc_kmeans(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(perturb), iters,
-                              _ptr(cen), _ptr(cnt), _ptr(lb)), "kmeans")
+    _check(_load().orc_kmeans_ex(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(dist),
+                                 int(perturb), iters, _ptr(cen), _ptr(cnt), _ptr(lb)), "kmeans")
     return lb, cen, cnt
 
 
@@ -227,15 +247,17 @@ def stray_filter(labels: np.ndarray, passes: int = 2) -> np.ndarray:
     return out
 
 
-def energy(lab, S: int, m: float, centres: np.ndarray, labels: np.ndarray) -> float:
-    """Mean Eq. 1 distance between each pixel and its associated centre."""
+def energy(lab, S: int, m: float, centres: np.ndarray, labels: np.ndarray,
+           dist: int = DIST_EQ1) -> float:
+    """Mean distance (Eq. 1, or the square root of the squared-sum form)
+    between each pixel and its associated centre."""
     L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
     h, w = L.shape
     cen = np.ascontiguousarray(centres, np.float32)
     lb = np.ascontiguousarray(labels, np.int32)
     out = ctypes.c_double()
-    _check(_load().orc_energy(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), _ptr(cen),
-                              cen.shape[0], _ptr(lb), ctypes.byref(out)), "energy")
+    _check(_load().orc_energy_ex(_ptr(L), _ptr(A), _ptr(B), w, h, S, float(m), int(dist),
+                                 _ptr(cen), cen.shape[0], _ptr(lb), ctypes.byref(out)), "energy")
     return float(out.value)
 
 
@@ -253,14 +275,15 @@ def connectivity(labels: np.ndarray, S: int, min_segment: int = 0):
 
 
 def segment(rgb: np.ndarray, S: int, m: float, iters: int, perturb: bool = True,
-            connectivity_on: bool = False, min_segment: int = 0):
+            connectivity_on: bool = False, min_segment: int = 0, space: int = COLOR_LAB,
+            dist: int = DIST_EQ1):
     """The whole path of Section 4's listing.  Returns a dict with lab, labels
     (after the k-means loop), centres, counts, energy and, when
     ``connectivity_on``, seg_labels / n_segments / seg_cluster."""
-    lab = rgb_to_lab(rgb)
-    labels, cen, cnt = kmeans(lab, S, m, perturb, iters)
+    lab = rgb_to_space(rgb, space) if space != COLOR_LAB else rgb_to_lab(rgb)
+    labels, cen, cnt = kmeans(lab, S, m, perturb, iters, dist)
     res = {"lab": lab, "labels": labels, "centres": cen, "counts": cnt,
-           "energy": energy(lab, S, m, cen, labels)}
+           "energy": energy(lab, S, m, cen, labels, dist)}
     if connectivity_on:
         seg, ns, sc = connectivity(labels, S, min_segment)
         res.update(seg_labels=seg, n_segments=ns, seg_cluster=sc)

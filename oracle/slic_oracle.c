@@ -170,6 +170,47 @@ int orc_rgb_to_lab(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int3
     return ORC_OK;
 }
 
+/* Other colour spaces (the listing's colour_space setting; the paper
+ * describes only CIELAB).  READING: space 1 is XYZ scaled by 100 (D65 white
+ * -> (100, 100, 100) with the row-normalised matrix above), computed in FP32
+ * in the order of the Lab path and then multiplied by 100; space 2 is the
+ * raw R, G, B bytes as floats.  Space 0 is CIELAB. */
+int orc_rgb_to_space(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int32_t channels,
+                     int32_t space, float* C0, float* C1, float* C2) {
+    if (space == 0) return orc_rgb_to_lab(rgb, w, h, pitch, channels, C0, C1, C2);
+    if (!rgb || !C0 || !C1 || !C2 || w < 1 || h < 1 || (channels != 3 && channels != 4) ||
+        pitch < w * channels || (space != 1 && space != 2))
+        return ORC_EINVAL;
+    float lin[256], nm[9];
+    orc_lab_tables(lin, nm);
+    for (int32_t y = 0; y < h; y++) {
+        for (int32_t x = 0; x < w; x++) {
+            const uint8_t* p = rgb + (size_t)y * pitch + (size_t)x * channels;
+            size_t i = (size_t)y * w + x;
+            if (space == 2) {
+                C0[i] = (float)p[0];
+                C1[i] = (float)p[1];
+                C2[i] = (float)p[2];
+                continue;
+            }
+            float r = lin[p[0]], g = lin[p[1]], b = lin[p[2]];
+            float X = nm[0] * r;
+            X = X + nm[1] * g;
+            X = X + nm[2] * b;
+            float Y = nm[3] * r;
+            Y = Y + nm[4] * g;
+            Y = Y + nm[5] * b;
+            float Z = nm[6] * r;
+            Z = Z + nm[7] * g;
+            Z = Z + nm[8] * b;
+            C0[i] = 100.0f * X;
+            C1[i] = 100.0f * Y;
+            C2[i] = 100.0f * Z;
+        }
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------
  * O2. Seeds (Section 2: centres on the S grid, perturbed to the lowest
  * gradient position in a local neighbourhood; Section 3: one thread per
@@ -264,10 +305,30 @@ static float orc_distance(const float* c, float l, float a, float b, int32_t x, 
     return dlab + sp;
 }
 
+/* The distance of the SLIC paper the method builds on, as an option:
+ * D^2 = d_lab^2 + (m/S)^2 d_xy^2 (the argmin of its square root), in FP32 in
+ * this order without square roots; its energy term is sqrt(D^2). */
+static float orc_distance_sq(const float* c, float l, float a, float b, int32_t x, int32_t y,
+                             float wgt) {
+    float dl = c[0] - l, da = c[1] - a, db = c[2] - b;
+    float s = orc_sq3(dl, da, db);
+    float dx = c[3] - (float)x, dy = c[4] - (float)y;
+    float t = dx * dx;
+    t = t + dy * dy;
+    float w2 = wgt * wgt;
+    float sp = w2 * t;
+    return s + sp;
+}
+
+static float orc_dist(int32_t dist, const float* c, float l, float a, float b, int32_t x,
+                      int32_t y, float wgt) {
+    return dist ? orc_distance_sq(c, l, a, b, x, y, wgt) : orc_distance(c, l, a, b, x, y, wgt);
+}
+
 float orc_weight(float m, int32_t S) { return m / (float)S; }
 
-int orc_assign(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
-               float m, const float* centres, int32_t* labels) {
+int orc_assign_ex(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+                  float m, int32_t dist, const float* centres, int32_t* labels) {
     if (!L || !A || !B || !centres || !labels || w < 1 || h < 1 || S < 1) return ORC_EINVAL;
     int32_t ns_c = (w + S - 1) / S, ns_r = (h + S - 1) / S;
     float wgt = orc_weight(m, S);
@@ -284,7 +345,7 @@ int orc_assign(const float* L, const float* A, const float* B, int32_t w, int32_
                     int32_t cx = gx + dx;
                     if (cx < 0 || cx >= ns_c) continue;
                     int32_t k = cy * ns_c + cx;
-                    float d = orc_distance(centres + 5 * (size_t)k, L[i], A[i], B[i], x, y, wgt);
+                    float d = orc_dist(dist, centres + 5 * (size_t)k, L[i], A[i], B[i], x, y, wgt);
                     if (bk < 0 || d < best) {
                         best = d;
                         bk = k;
@@ -295,6 +356,11 @@ int orc_assign(const float* L, const float* A, const float* B, int32_t w, int32_
         }
     }
     return ORC_OK;
+}
+
+int orc_assign(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+               float m, const float* centres, int32_t* labels) {
+    return orc_assign_ex(L, A, B, w, h, S, m, 0, centres, labels);
 }
 
 /* ------------------------------------------------------------------------
@@ -356,23 +422,29 @@ int orc_update(const float* L, const float* A, const float* B, int32_t w, int32_
  * iters == 0).  READING: a fixed iteration count; the L1 stopping threshold
  * of Section 2 is a separate option.
  * ---------------------------------------------------------------------- */
-int orc_kmeans(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
-               float m, int32_t perturb, int32_t iters, float* centres, int32_t* counts,
-               int32_t* labels) {
+int orc_kmeans_ex(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+                  float m, int32_t dist, int32_t perturb, int32_t iters, float* centres,
+                  int32_t* counts, int32_t* labels) {
     if (w < 1 || h < 1 || S < 1 || iters < 0) return ORC_EINVAL;
     int32_t K = ((w + S - 1) / S) * ((h + S - 1) / S);
     int rc = orc_seed(L, A, B, w, h, S, perturb, centres);
     if (rc) return rc;
     for (int32_t k = 0; k < K; k++) counts[k] = 0;
-    rc = orc_assign(L, A, B, w, h, S, m, centres, labels);
+    rc = orc_assign_ex(L, A, B, w, h, S, m, dist, centres, labels);
     if (rc) return rc;
     for (int32_t it = 0; it < iters; it++) {
         rc = orc_update(L, A, B, w, h, labels, K, centres, counts);
         if (rc) return rc;
-        rc = orc_assign(L, A, B, w, h, S, m, centres, labels);
+        rc = orc_assign_ex(L, A, B, w, h, S, m, dist, centres, labels);
         if (rc) return rc;
     }
     return ORC_OK;
+}
+
+int orc_kmeans(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+               float m, int32_t perturb, int32_t iters, float* centres, int32_t* counts,
+               int32_t* labels) {
+    return orc_kmeans_ex(L, A, B, w, h, S, m, 0, perturb, iters, centres, counts, labels);
 }
 
 /* ------------------------------------------------------------------------
@@ -422,8 +494,9 @@ int orc_kmeans_converge(const float* L, const float* A, const float* B, int32_t 
  * centre it is associated with, each term computed exactly as in O3 and
  * summed in FP64 in raster order.
  * ---------------------------------------------------------------------- */
-int orc_energy(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
-               float m, const float* centres, int32_t K, const int32_t* labels, double* out) {
+int orc_energy_ex(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+                  float m, int32_t dist, const float* centres, int32_t K, const int32_t* labels,
+                  double* out) {
     if (!L || !A || !B || !centres || !labels || !out || w < 1 || h < 1 || S < 1) return ORC_EINVAL;
     float wgt = orc_weight(m, S);
     double acc = 0.0;
@@ -432,11 +505,17 @@ int orc_energy(const float* L, const float* A, const float* B, int32_t w, int32_
             size_t i = (size_t)y * w + x;
             int32_t k = labels[i];
             if (k < 0 || k >= K) return ORC_EINVAL;
-            acc += (double)orc_distance(centres + 5 * (size_t)k, L[i], A[i], B[i], x, y, wgt);
+            float d = orc_dist(dist, centres + 5 * (size_t)k, L[i], A[i], B[i], x, y, wgt);
+            acc += (double)(dist ? sqrtf(d) : d);
         }
     }
     *out = acc / ((double)w * (double)h);
     return ORC_OK;
+}
+
+int orc_energy(const float* L, const float* A, const float* B, int32_t w, int32_t h, int32_t S,
+               float m, const float* centres, int32_t K, const int32_t* labels, double* out) {
+    return orc_energy_ex(L, A, B, w, h, S, m, 0, centres, K, labels, out);
 }
 
 /* ------------------------------------------------------------------------

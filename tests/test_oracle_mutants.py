@@ -15,6 +15,7 @@ import test_oracle_lab as tl
 import test_oracle_net as tn
 import test_oracle_seed as ts
 import test_oracle_update as tu
+import test_oracle_variants as tv
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "slic_oracle.c")
 NET_SRC = os.path.join(os.path.dirname(oracle.__file__), "net_oracle.c")
@@ -29,9 +30,13 @@ MUTANTS = [
     ("gradient_clamp", "xl = x > 0 ? x - 1 : 0", "xl = x > 0 ? x - 1 : 1", ["seed"]),
     ("seed_tiebreak", "if (g < gbest)", "if (g <= gbest)", ["seed"]),
     ("seed_middle", "sx = x0 + (x1 - x0 - 1) / 2", "sx = x0 + (x1 - x0) / 2", ["seed"]),
-    ("distance_operand", "db = c[2] - b;", "db = c[2] - a;", ["assign"]),
+    ("distance_operand", "db = c[2] - b;\n    float dlab", "db = c[2] - a;\n    float dlab",
+     ["assign"]),
     ("distance_weight", "float sp = wgt * dxy;", "float sp = dxy;", ["assign"]),
-    ("distance_dy", "dy = c[4] - (float)y;", "dy = c[4] - (float)x;", ["assign"]),
+    ("distance_dy", "dy = c[4] - (float)y;\n    float s = dx * dx;",
+     "dy = c[4] - (float)x;\n    float s = dx * dx;", ["assign"]),
+    ("distance_sq_weight", "float w2 = wgt * wgt;", "float w2 = wgt;", ["variants"]),
+    ("xyz_scale", "C1[i] = 100.0f * Y;", "C1[i] = 10.0f * Y;", ["variants"]),
     ("assign_tiebreak", "if (bk < 0 || d < best)", "if (bk < 0 || d <= best)", ["assign"]),
     ("assign_window", "for (int32_t dx = -1; dx <= 1; dx++) {\n                    int32_t cx",
      "for (int32_t dx = -1; dx <= 0; dx++) {\n                    int32_t cx", ["assign"]),
@@ -84,6 +89,10 @@ PINS = {
                lambda: tu.test_uniform_image_centres_land_on_cell_middles(15, 9, 3)],
     "net": [lambda: [tn.test_backward_matches_central_differences(s) for s in range(2)],
             lambda: [tn.test_forward_matches_scipy_correlation(s) for s in range(2)]],
+    "variants": [tv.test_xyz_white_black_grey, tv.test_xyz_is_additive_over_the_primaries,
+                 lambda: [tv.test_squared_association_is_the_nearest_candidate(m)
+                          for m in (10.0, 40.0)],
+                 tv.test_squared_energy_is_the_mean_root],
     "ccl": [lambda: [tc.test_matches_independent_statement(s) for s in range(40)],
             lambda: [tc.test_invariants(s) for s in range(5)],
             lambda: [tc.test_energy_is_the_mean_eq1_distance(s) for s in range(3)]],
