@@ -46,8 +46,16 @@ enum {
 };
 
 enum {
-    SLIC_PERTURB_SEEDS = 1 /* move each seed to the lowest-gradient pixel of its 3x3 window
-                              (Section 2, "perturbed to the lowest gradient position") */
+    SLIC_PERTURB_SEEDS = 1,   /* move each seed to the lowest-gradient pixel of its 3x3 window
+                                 (Section 2, "perturbed to the lowest gradient position") */
+    /* colour planes other than CIELAB (the listing's colour-space setting):
+     * XYZ scaled by 100 (D65 white -> 100, 100, 100), or the R, G, B bytes
+     * as floats; at most one of the two */
+    SLIC_COLOR_XYZ = 2,
+    SLIC_COLOR_RGB = 4,
+    /* the distance of the SLIC paper the method builds on instead of Eq. 1:
+     * D^2 = d_lab^2 + (m/S)^2 d_xy^2 (same candidates; its energy term is D) */
+    SLIC_DISTANCE_SQUARED = 8
 };
 
 /* The problem statement of Section 2: an image of N = width*height pixels,
@@ -61,7 +69,8 @@ typedef struct {
     int32_t K;             /* desired superpixel count, used only when S == 0:
                               S = max(1, floor(sqrt(N/K) + 0.5)) */
     float m;               /* compactness, finite and >= 0 */
-    int32_t flags;         /* SLIC_PERTURB_SEEDS or 0 */
+    int32_t flags;         /* SLIC_PERTURB_SEEDS, SLIC_COLOR_XYZ or SLIC_COLOR_RGB,
+                              SLIC_DISTANCE_SQUARED, or 0 (a batch shares one distance) */
     int32_t min_segment;   /* connectivity: components smaller than this many pixels
                               are merged; 0: merge when 4*size < S*S */
 } slic_params;

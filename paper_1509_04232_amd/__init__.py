@@ -11,8 +11,8 @@ import dataclasses
 import torch
 
 from . import _abi
-from ._abi import (EXPORTED, SLIC_EHIP, SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, SLIC_OK,
-                   SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_assign_variant_info,
+from ._abi import (EXPORTED, SLIC_COLOR_RGB, SLIC_COLOR_XYZ, SLIC_DISTANCE_SQUARED, SLIC_EHIP,
+                   SLIC_EINVAL, SLIC_ENOMEM, SLIC_ESTATE, SLIC_OK, SLIC_PERTURB_SEEDS, SlicError, SlicParams, slic_assign_variant_info,
                    slic_assign_variants, slic_autotune, slic_batch_autotune, slic_batch_create,
                    slic_batch_destroy, slic_batch_run, slic_batch_workspace_bytes,
                    slic_destroy, slic_filter_stray, slic_segment_batch,
@@ -46,12 +46,16 @@ class Params:
     min_segment: int = 0
     channels: int = 3
     pitch: int | None = None
+    color: str = "lab"          # "lab", "xyz" or "rgb"
+    squared_distance: bool = False
 
     def c(self) -> SlicParams:
+        flags = SLIC_PERTURB_SEEDS if self.perturb else 0
+        flags |= {"lab": 0, "xyz": SLIC_COLOR_XYZ, "rgb": SLIC_COLOR_RGB}[self.color]
+        flags |= SLIC_DISTANCE_SQUARED if self.squared_distance else 0
         return SlicParams(self.width, self.height,
                           self.pitch if self.pitch is not None else self.width * self.channels,
-                          self.channels, self.S, self.K, float(self.m),
-                          SLIC_PERTURB_SEEDS if self.perturb else 0, self.min_segment)
+                          self.channels, self.S, self.K, float(self.m), flags, self.min_segment)
 
     def grid(self):
         return slic_grid(self.c())

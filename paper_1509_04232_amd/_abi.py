@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libslic.so")
 
 SLIC_OK, SLIC_EINVAL, SLIC_ENOMEM, SLIC_EHIP, SLIC_ESTATE = 0, 1, 2, 3, 4
 SLIC_PERTURB_SEEDS = 1
+SLIC_COLOR_XYZ, SLIC_COLOR_RGB, SLIC_DISTANCE_SQUARED = 2, 4, 8
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; "

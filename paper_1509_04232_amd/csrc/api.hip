@@ -116,6 +116,8 @@ bool compute_grid(const slic_params* p, Grid* g) {
     g->ns_r = static_cast<int32_t>((static_cast<int64_t>(p->height) + S - 1) / S);
     g->K = g->ns_c * g->ns_r;
     g->w = p->m / static_cast<float>(S);
+    g->space = (p->flags & SLIC_COLOR_XYZ) ? 1 : (p->flags & SLIC_COLOR_RGB) ? 2 : 0;
+    g->dist = (p->flags & SLIC_DISTANCE_SQUARED) ? 1 : 0;
     return true;
 }
 
@@ -128,7 +130,9 @@ bool params_ok(const slic_params* p) {
     if (static_cast<int64_t>(p->pitch) < static_cast<int64_t>(p->width) * p->channels) return false;
     if (p->S < 0 || (p->S == 0 && p->K < 1)) return false;
     if (!std::isfinite(p->m) || p->m < 0.0f) return false;
-    if (p->flags & ~SLIC_PERTURB_SEEDS) return false;
+    if (p->flags & ~(SLIC_PERTURB_SEEDS | SLIC_COLOR_XYZ | SLIC_COLOR_RGB | SLIC_DISTANCE_SQUARED))
+        return false;
+    if ((p->flags & SLIC_COLOR_XYZ) && (p->flags & SLIC_COLOR_RGB)) return false;
     if (p->min_segment < 0) return false;
     return true;
 }
@@ -351,7 +355,7 @@ hipError_t batch_enqueue(const slic_batch* b, hipStream_t s) {
     hipError_t e = launch_lab_seed_batch(lmap, b->lab_tiles, s);
     const AssignTileMap amap{b->asg_images, b->asg_tile_image, b->asg_tile_first};
     for (int t = 0; e == hipSuccess && t <= b->n_iters; ++t)
-        e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, s);
+        e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, b->grids[0].dist, s);
     for (int i = 0; e == hipSuccess && b->enforce && i < b->n; ++i) {
         Workspace w = b->ws[i];
         w.labels = b->labels[i];
@@ -593,7 +597,8 @@ int check_warm_args(const slic_params* p, const uint8_t* d_rgb, const void* d_ne
         return SLIC_EINVAL;
     Grid g;
     compute_grid(p, &g);
-    if (!warm_supported(g.S) || ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    if (!warm_supported(g.S) || g.space != 0 || g.dist != 0 || ws_bytes < slic_workspace_bytes(p))
+        return SLIC_EINVAL;
     int rc = check_buffers(d_rgb, d_ws);
     if (rc) return rc;
     return check_device_ptr(d_net);
@@ -605,7 +610,7 @@ size_t slic_warm_workspace_bytes(const slic_params* p) {
     if (!params_ok(p)) return 0;
     Grid g;
     compute_grid(p, &g);
-    return warm_supported(g.S) ? slic_workspace_bytes(p) : 0;
+    return warm_supported(g.S) && g.space == 0 && g.dist == 0 ? slic_workspace_bytes(p) : 0;
 }
 
 int slic_warm_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, const void* d_net,
@@ -764,8 +769,12 @@ int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_
     *out = nullptr;
     const size_t need = slic_batch_workspace_bytes(per_image, n_images);
     if (need == 0 || ws_bytes < need) return SLIC_EINVAL;
-    for (int i = 0; i < n_images; ++i)
+    for (int i = 0; i < n_images; ++i) {
         if (!d_rgb[i] || !d_labels[i]) return SLIC_EINVAL;
+        // one association kernel serves the whole batch: one distance form
+        if ((per_image[i].flags & SLIC_DISTANCE_SQUARED) != (per_image[0].flags & SLIC_DISTANCE_SQUARED))
+            return SLIC_EINVAL;
+    }
     int rc = check_device_ptr(d_ws);
     for (int i = 0; rc == SLIC_OK && i < n_images; ++i) {
         rc = check_device_ptr(d_rgb[i]);

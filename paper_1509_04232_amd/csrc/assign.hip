@@ -139,7 +139,24 @@ __device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, in
     atomicAdd(bins + 3 * ncells + cell, rxyc);
 }
 
-template <int VEC, int ROWS>
+// The squared-sum distance of the SLIC paper the method builds on (an
+// option): d_lab^2 + w^2 d_xy^2 in FP32 in this order, no square roots, so
+// its argmin is taken exactly.
+__device__ __forceinline__ float dist_squared(float cl, float ca, float cb, float cx, float dy2,
+                                              float l, float a, float b, float xf, float wgt) {
+    const float dl = cl - l, da = ca - a, db = cb - b;
+    float s = dl * dl;
+    s = s + da * da;
+    s = s + db * db;
+    const float dx = cx - xf;
+    float t = dx * dx;
+    t = t + dy2;
+    const float w2 = wgt * wgt;
+    const float sp = w2 * t;
+    return s + sp;
+}
+
+template <int VEC, int ROWS, int DIST>
 __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, AssignTileMap map,
                                                           long long t, Converge cv) {
     using Sh = Shape<VEC, ROWS>;
@@ -283,6 +300,34 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         const int y = y0 + ty * ROWS + r;
         const float yf = static_cast<float>(y);
         const int base = (min(y, g.h - 1) / S - gy_lo - 1) * ncx + gx_rel;
+        if constexpr (DIST == 1) {
+            // exact: (distance bits, slot) as one 64-bit key, lowest slot on ties
+            unsigned long long bk[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) bk[v] = ~0ull;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const int li = base + (c / 3) * ncx + (c % 3);
+                const float4 q = cen4[li];
+                const float dy = ceny[li] - yf;
+                const float dy2 = dy * dy;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const float d = dist_squared(q.x, q.y, q.z, q.w, dy2, pl[r][v], pa[r][v],
+                                                 pb[r][v], static_cast<float>(x + v), g.wgt);
+                    const unsigned long long key =
+                        (static_cast<unsigned long long>(__float_as_uint(d)) << 4) |
+                        static_cast<unsigned long long>(c);
+                    bk[v] = key < bk[v] ? key : bk[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                const int slot = static_cast<int>(bk[v] & 15ull);
+                cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
+            }
+            continue;
+        }
         unsigned best[VEC], second[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) best[v] = second[v] = 0xFFFFFFFFu;
@@ -389,16 +434,22 @@ constexpr int kEnergyBlock = 256;
 
 __global__ __launch_bounds__(kEnergyBlock) void energy_kernel(
     const float* __restrict__ L, const float* __restrict__ A, const float* __restrict__ B, int w,
-    int n, float wgt, const float* __restrict__ cen, const int32_t* __restrict__ labels,
+    int n, float wgt, int dist, const float* __restrict__ cen, const int32_t* __restrict__ labels,
     double* __restrict__ partial) {
     __shared__ double red[kEnergyBlock];
     const int i = blockIdx.x * kEnergyBlock + threadIdx.x;
     double v = 0.0;
     if (i < n) {
         const float* c = cen + static_cast<size_t>(labels[i]) * kCenStride;
-        v = static_cast<double>(eq1_reference(c[0], c[1], c[2], c[3], c[4], L[i], A[i], B[i],
-                                              static_cast<float>(i % w),
-                                              static_cast<float>(i / w), wgt));
+        const float xf = static_cast<float>(i % w), yf = static_cast<float>(i / w);
+        if (dist) {
+            const float dy = c[4] - yf;
+            v = static_cast<double>(
+                sqrtf(dist_squared(c[0], c[1], c[2], c[3], dy * dy, L[i], A[i], B[i], xf, wgt)));
+        } else {
+            v = static_cast<double>(eq1_reference(c[0], c[1], c[2], c[3], c[4], L[i], A[i], B[i],
+                                                  xf, yf, wgt));
+        }
     }
     red[threadIdx.x] = v;
     __syncthreads();
@@ -450,7 +501,7 @@ size_t variant_lds(int S) {
     return assign_lds_bytes(((Sh::kTileW - 1) / S + 4) * ((Sh::kTileH - 1) / S + 4));
 }
 
-template <int VEC, int ROWS>
+template <int VEC, int ROWS, int DIST>
 hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int total_tiles,
                           int min_S, long long t, const Converge& cv, hipStream_t s) {
     using Sh = Shape<VEC, ROWS>;
@@ -461,24 +512,26 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
         grid = dim3((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
     }
     KernelTimer timer("assign", s);
-    assign_kernel<VEC, ROWS><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t, cv);
+    assign_kernel<VEC, ROWS, DIST><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t,
+                                                                                       cv);
     return hipGetLastError();
 }
+
+using LaunchFn = hipError_t (*)(const AssignImage&, const AssignTileMap&, int, int, long long,
+                                const Converge&, hipStream_t);
 
 struct VariantDesc {
     int vec, rows;
     size_t (*lds)(int);
-    hipError_t (*launch)(const AssignImage&, const AssignTileMap&, int, int, long long,
-                         const Converge&,
-                         hipStream_t);
+    LaunchFn launch[2];  // Eq. 1, squared-sum distance
 };
 
 const VariantDesc kVariants[] = {
-    {1, 1, variant_lds<1, 1>, launch_variant<1, 1>},
-    {1, 2, variant_lds<1, 2>, launch_variant<1, 2>},
-    {1, 4, variant_lds<1, 4>, launch_variant<1, 4>},
-    {4, 1, variant_lds<4, 1>, launch_variant<4, 1>},
-    {4, 2, variant_lds<4, 2>, launch_variant<4, 2>},
+    {1, 1, variant_lds<1, 1>, {launch_variant<1, 1, 0>, launch_variant<1, 1, 1>}},
+    {1, 2, variant_lds<1, 2>, {launch_variant<1, 2, 0>, launch_variant<1, 2, 1>}},
+    {1, 4, variant_lds<1, 4>, {launch_variant<1, 4, 0>, launch_variant<1, 4, 1>}},
+    {4, 1, variant_lds<4, 1>, {launch_variant<4, 1, 0>, launch_variant<4, 1, 1>}},
+    {4, 2, variant_lds<4, 2>, {launch_variant<4, 2, 0>, launch_variant<4, 2, 1>}},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -550,15 +603,15 @@ hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     const AssignImage a = assign_image(ws, w, h, g, variant);
     const AssignTileMap none{nullptr, nullptr, nullptr};
     const Converge off{nullptr, 0, 0};
-    return kVariants[variant - 1].launch(a, none, 0, g.S, t, cv ? *cv : off, s);
+    return kVariants[variant - 1].launch[g.dist ? 1 : 0](a, none, 0, g.S, t, cv ? *cv : off, s);
 }
 
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
-                               int variant, hipStream_t s) {
+                               int variant, int dist, hipStream_t s) {
     if (variant < 1 || variant > kNumVariants || !map.images) return hipErrorInvalidValue;
     AssignImage unused{};
     const Converge off{nullptr, 0, 0};
-    return kVariants[variant - 1].launch(unused, map, total_tiles, min_S, t, off, s);
+    return kVariants[variant - 1].launch[dist ? 1 : 0](unused, map, total_tiles, min_S, t, off, s);
 }
 
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,
@@ -567,8 +620,8 @@ hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     const int nb = (n + kEnergyBlock - 1) / kEnergyBlock;
     {
         KernelTimer t("energy", s);
-        energy_kernel<<<nb, kEnergyBlock, 0, s>>>(ws.L, ws.A, ws.B, w, n, g.w, ws.cen, ws.labels,
-                                                  ws.partial);
+        energy_kernel<<<nb, kEnergyBlock, 0, s>>>(ws.L, ws.A, ws.B, w, n, g.w, g.dist, ws.cen,
+                                                  ws.labels, ws.partial);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

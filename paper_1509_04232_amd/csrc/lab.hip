@@ -8,7 +8,9 @@
 // linear segment below), then L = 116 fy - 16, a = 500 (fx - fy),
 // b = 200 (fy - fz) in FP32.  Every operation is IEEE round-to-nearest in
 // the order written; the file is compiled without FMA contraction (the cube
-// root's fused multiply-adds are explicit).
+// root's fused multiply-adds are explicit).  The colour-space option yields
+// XYZ scaled by 100 (same order, then the scaling) or the R, G, B bytes as
+// floats instead; the seeds and the gradient work on whichever planes.
 //
 // Seeds: the seed of cell (cx, cy) is the cell's middle pixel
 // x0 + (x1 - x0 - 1) / 2 (likewise in y), the cell spanning [x0, x1)
@@ -124,6 +126,24 @@ __device__ __forceinline__ void rgb_to_lab(const float* lin, const float* nm, co
     *B = 200.0f * dyz;
 }
 
+// XYZ scaled by 100 (the colour-space option), in the Lab path's order.
+__device__ __forceinline__ void rgb_to_xyz100(const float* lin, const float* nm, const uint8_t* p,
+                                              float* X0, float* Y0, float* Z0) {
+    const float r = lin[p[0]], g = lin[p[1]], b = lin[p[2]];
+    float X = nm[0] * r;
+    X = X + nm[1] * g;
+    X = X + nm[2] * b;
+    float Y = nm[3] * r;
+    Y = Y + nm[4] * g;
+    Y = Y + nm[5] * b;
+    float Z = nm[6] * r;
+    Z = Z + nm[7] * g;
+    Z = Z + nm[8] * b;
+    *X0 = 100.0f * X;
+    *Y0 = 100.0f * Y;
+    *Z0 = 100.0f * Z;
+}
+
 __device__ __forceinline__ float norm2(float u, float v, float t) {
     float a = u * u;
     a = a + v * v;
@@ -163,9 +183,16 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single,
         const int x = x0 - kHalo + i % kSW, y = y0 - kHalo + i / kSW;
         if (x < 0 || y < 0 || x >= g.w || y >= g.h) continue;
         float l, a, b;
-        rgb_to_lab(lin, tab.nm,
-                   g.rgb + static_cast<size_t>(y) * g.pitch + static_cast<size_t>(x) * g.channels,
-                   &l, &a, &b);
+        const uint8_t* px = g.rgb + static_cast<size_t>(y) * g.pitch + static_cast<size_t>(x) * g.channels;
+        if (g.space == 0) {
+            rgb_to_lab(lin, tab.nm, px, &l, &a, &b);
+        } else if (g.space == 1) {
+            rgb_to_xyz100(lin, tab.nm, px, &l, &a, &b);
+        } else {
+            l = static_cast<float>(px[0]);
+            a = static_cast<float>(px[1]);
+            b = static_cast<float>(px[2]);
+        }
         sL[i] = l;
         sA[i] = a;
         sB[i] = b;
@@ -269,6 +296,7 @@ LabSeedImage lab_seed_image(const uint8_t* rgb, int32_t w, int32_t h, int32_t pi
     a.ns_c = grid.ns_c;
     a.ns_r = grid.ns_r;
     a.perturb = perturb;
+    a.space = grid.space;
     a.cen = ws.cen;
     a.counts = ws.counts;
     a.sums = ws.sums;

@@ -24,7 +24,9 @@ constexpr int kSumStride = 6;
 
 struct Grid {
     int32_t S, ns_c, ns_r, K;
-    float w;  // m / S in FP32, the factor of d_xy in Eq. 1
+    float w;      // m / S in FP32, the factor of d_xy in Eq. 1
+    int32_t space;  // colour planes: 0 CIELAB, 1 XYZ x 100, 2 the RGB bytes
+    int32_t dist;   // 0 Eq. 1, 1 the squared-sum form d_lab^2 + w^2 d_xy^2
 };
 
 struct Workspace {
@@ -53,7 +55,7 @@ struct LabSeedImage {
     const uint8_t* rgb;
     int w, h, pitch, channels;
     float *L, *A, *B;
-    int S, ns_c, ns_r, perturb;
+    int S, ns_c, ns_r, perturb, space;
     float* cen;
     int32_t* counts;
     long long* sums;  // first accumulator buffer
@@ -116,7 +118,7 @@ hipError_t launch_converge_result(const long long* ctl, int32_t max_iters, int32
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
                          int variant, hipStream_t s, const Converge* cv = nullptr);
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
-                               int variant, hipStream_t s);
+                               int variant, int dist, hipStream_t s);
 AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant);
 bool assign_tiles(int variant, int32_t w, int32_t h, int* tiles_x, int* tiles_y);
 int assign_variant_count();

@@ -50,7 +50,7 @@ def test_grid_matches_oracle_reading(abi, w, h, S, K):
 
 @pytest.mark.parametrize("bad", [dict(width=0), dict(height=-1), dict(channels=2),
                                  dict(pitch=10), dict(S=-1), dict(S=0, K=0), dict(m=-1.0),
-                                 dict(m=float("nan")), dict(m=float("inf")), dict(flags=2),
+                                 dict(m=float("nan")), dict(m=float("inf")), dict(flags=16), dict(flags=6),
                                  dict(min_segment=-1), dict(width=1 << 25, height=1),
                                  dict(width=40000, height=40000)])
 def test_invalid_params_rejected(abi, bad):
