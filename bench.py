@@ -48,7 +48,7 @@ def assign_bytes(n_pixels: int, n_clusters: int) -> int:
 class Frame:
     """Preallocated buffers for repeated slic_segment calls on one image."""
 
-    def __init__(self, slic, wl, device):
+    def __init__(self, slic, wl, device, squared_distance: bool = False):
         import numpy as np  # noqa: F401
         import torch
 
@@ -58,7 +58,7 @@ class Frame:
         img = synth.image_for(wl)
         self.rgb = torch.from_numpy(img.reshape(-1)).to(device)
         self.p = slic.Params(wl.width, wl.height, S=wl.S, m=wl.m, perturb=wl.perturb,
-                             min_segment=wl.min_segment)
+                             min_segment=wl.min_segment, squared_distance=squared_distance)
         self.cp = self.p.c()
         self.ws = slic.workspace_for(self.p, device)
         self.labels = torch.empty((wl.height, wl.width), dtype=torch.int32, device=device)
@@ -374,6 +374,61 @@ def bench_video(slic, torch, dev, n_frames: int, rounds: int, reps: int):
             "frames_within_1pct": int((ratio <= 1.01).sum())}
 
 
+def bench_cleanup(slic, torch, dev, reps: int):
+    """Row f2: the paper's stray-pixel filter (two passes) against the
+    connectivity merge on c2 labels after 10 rounds: kernel time per frame
+    (HIP events around each launch) and the 4-connected components each
+    leaves, with those under the merge threshold S*S/4."""
+    import numpy as np
+    from scipy import ndimage
+
+    import synth
+    wl = synth.WORKLOADS["c2"]
+    rgb = torch.from_numpy(synth.image_for(wl).reshape(-1)).to(dev)
+    p = slic.Params(wl.width, wl.height, S=wl.S, m=wl.m)
+
+    def run(kind, timed):
+        ctx = slic.Context(p, rgb)
+        ctx.iterate(wl.iters)
+        if timed:
+            slic.slic_timing_enable(True)
+        if kind == "stray":
+            ctx.filter_stray(2)
+        else:
+            ctx.enforce_connectivity()
+        if timed:
+            slic.slic_timing_enable(False)
+        out = ctx.labels()
+        ctx.close()
+        return out
+
+    def components(lb):
+        n_all = n_small = 0
+        for v in np.unique(lb):
+            comp, n = ndimage.label(lb == v)
+            sizes = np.bincount(comp.ravel())[1:]
+            n_all += n
+            n_small += int((4 * sizes < wl.S * wl.S).sum())
+        return n_all, n_small
+
+    res = {}
+    for kind, prefix in (("stray", "stray"), ("merge", "ccl_")):
+        run(kind, False)
+        total, launches = 0.0, 0
+        for _ in range(reps):
+            run(kind, True)
+            ms, n = slic.slic_timing_read(prefix)
+            total += ms
+            launches += n
+        lb = run(kind, False).cpu().numpy()
+        n_all, n_small = components(lb)
+        res[kind] = {"us_per_frame": round(total / reps * 1e3, 2), "launches": launches // reps,
+                     "components": n_all, "components_below_threshold": n_small}
+    raw = slic.segment(rgb, p, wl.iters)["labels"].cpu().numpy()
+    res["before"] = dict(zip(("components", "components_below_threshold"), components(raw)))
+    return res
+
+
 def traffic_from_profile():
     """HBM bytes per association launch from the committed PMC summary, or
     None if it is missing or the kernel source changed since."""
@@ -511,11 +566,22 @@ def main() -> int:
                 entry["assign_variant"] = f.variant
                 entry["assign_gbps"] = round(b / (a * 1e-3) / 1e9, 1)
                 entry["assign_hbm_frac"] = round(b / (a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+            if name == "c3":
+                # row f4: the squared-sum distance (no square roots) at 1080p
+                fq = Frame(slic, w, dev, squared_distance=True)
+                tq = (time_frames(torch, fq, steps, 5, 10, False) -
+                      time_frames(torch, fq, steps, 5, 0, False)) / 10
+                aq = assign_launch_ms(slic, torch, fq)
+                entry["squared_distance"] = {
+                    "mpix_per_s_per_iter": round(w.n_pixels / tq / 1e6, 1),
+                    "us_per_iter": round(tq * 1e6, 3), "assign_avg_us": round(aq * 1e3, 3),
+                    "assign_variant": fq.variant}
             extra[name] = entry
         extra["c4"] = bench_c4(slic, torch, dev, reps=max(5, args.steps // 50))
         extra["c5"] = bench_c5(slic, torch, dev, args.train_steps, args.train_images, 32,
                                reps=max(3, args.steps // 100))
         extra["video"] = bench_video(slic, torch, dev, 32, 2, reps=max(3, args.steps // 100))
+        extra["cleanup_c2"] = bench_cleanup(slic, torch, dev, reps=20)
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
