@@ -47,7 +47,7 @@ enum {
 
 enum {
     SLIC_PERTURB_SEEDS = 1,   /* move each seed to the lowest-gradient pixel of its 3x3 window
-                                 (Section 2, "perturbed to the lowest gradient position") */
+                                 (Section 2's seed perturbation) */
     /* colour planes other than CIELAB (the listing's colour-space setting):
      * XYZ scaled by 100 (D65 white -> 100, 100, 100), or the R, G, B bytes
      * as floats; at most one of the two */
@@ -131,7 +131,7 @@ int slic_iterate_converge(slic_ctx* ctx, int32_t max_iters, float threshold,
  * return SLIC_ESTATE; the centres stay those of the last association. */
 int slic_enforce_connectivity(slic_ctx* ctx, int32_t* d_n_segments);
 
-/* The paper's own clean-up (Section 3, "Enforce connectivity"), a cheaper
+/* The paper's own clean-up (Section 3's connectivity step), a cheaper
  * alternative to slic_enforce_connectivity that does not guarantee
  * connected segments: `passes` (>= 0; the paper uses 2) one-thread-per-pixel
  * passes in which a pixel none of whose 4-neighbours inside the image shares

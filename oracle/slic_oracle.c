@@ -448,8 +448,8 @@ int orc_kmeans(const float* L, const float* A, const float* B, int32_t w, int32_
 }
 
 /* ------------------------------------------------------------------------
- * Convergence stop (Section 2: the loop ends once the L1 distance between
- * the centres of consecutive iterations falls below a threshold).
+ * Convergence stop (Section 2 ends the loop once the centres move by less
+ * than a threshold in L1 from one iteration to the next).
  * READING: the distance is summed over every centre and its five components
  * (L, a, b, x, y), each |difference| taken in FP64 and quantised to
  * rint(|d| * 2^18) so that the sum is an exact integer; the threshold T is
@@ -598,10 +598,9 @@ int orc_connectivity(const int32_t* labels, int32_t w, int32_t h, int32_t S, int
 }
 
 /* ------------------------------------------------------------------------
- * Stray-pixel filter (Section 3, "Enforce connectivity": two one-thread-
- * per-pixel calls of one kernel; a pixel takes the label of the surrounding
- * pixels when all of them carry a different label).
- * READING: the surrounding pixels are the 4-connected neighbours inside the
+ * Stray-pixel filter (Section 3's clean-up step: a pixel whose neighbours
+ * all carry other labels adopts theirs; the same per-pixel pass runs twice).
+ * READING: the neighbours are the 4-connected ones inside the
  * image (up, left, right, down).  A pixel none of whose neighbours shares its
  * label takes the label that occurs most often among them, ties going to the
  * first in the order up, left, right, down; every pixel decides from the

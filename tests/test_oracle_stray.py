@@ -1,5 +1,5 @@
-"""Pins of the stray-pixel filter (Section 3: a pixel takes the surrounding
-label when none of its 4-neighbours shares its label): hand-worked cases,
+"""Pins of the stray-pixel filter (Section 3's clean-up step: a pixel none of
+whose 4-neighbours shares its label adopts theirs): hand-worked cases,
 border pixels, majority and tie order, and invariants on random maps (the
 pixels a pass changes are exactly those without a same-label neighbour,
 computed here with array shifts; two passes equal one pass applied twice)."""
