@@ -93,6 +93,36 @@ __device__ __noinline__ int reference_slot(const float4* cen4, const float* ceny
     return sref;
 }
 
+// Global (device) memory as a named address space: accesses through such
+// pointers compile to global rather than flat memory instructions (flat ones
+// also count against the LDS wait counter, so every LDS wait would wait for
+// them too).
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <class T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+    return (gmem<T>*)p;
+}
+
+// 16-byte global accesses (builtin vector types: HIP's float4 and int4 are
+// classes whose members assume generic pointers).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef int vi4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_f4(gmem<const float>* p) {
+    const vf4 v = *reinterpret_cast<gmem<const vf4>*>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void store_f4(gmem<float>* p, float4 v) {
+    *reinterpret_cast<gmem<vf4>*>(p) = vf4{v.x, v.y, v.z, v.w};
+}
+
+__device__ __forceinline__ void store_i4(gmem<int32_t>* p, int a, int b, int c, int d) {
+    *reinterpret_cast<gmem<vi4>*>(p) = vi4{a, b, c, d};
+}
+
 // A workgroup's image: from the kernel argument (one image) or, for a batch,
 // from the image table through the tile-to-image map.
 __device__ __forceinline__ void resolve_image(const AssignImage& single, const AssignTileMap& map,
@@ -131,11 +161,12 @@ struct Shape {
     static constexpr int kPx = VEC * ROWS;
 };
 
-__device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, int cell, int rl,
-                                        int ra, int rb, unsigned long long rxyc) {
-    atomicAdd(bins + cell, static_cast<unsigned long long>(static_cast<long long>(rl)));
-    atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(static_cast<long long>(ra)));
-    atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(static_cast<long long>(rb)));
+__device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, int cell,
+                                        long long rl, long long ra, long long rb,
+                                        unsigned long long rxyc) {
+    atomicAdd(bins + cell, static_cast<unsigned long long>(rl));
+    atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(ra));
+    atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(rb));
     atomicAdd(bins + 3 * ncells + cell, rxyc);
 }
 
@@ -156,9 +187,11 @@ __device__ __forceinline__ float dist_squared(float cl, float ca, float cb, floa
     return s + sp;
 }
 
+// The Eq. 1 variants are held to 128 VGPRs (four waves per SIMD), which
+// they need for latency hiding at large frames.
 template <int VEC, int ROWS, int DIST>
-__global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, AssignTileMap map,
-                                                          long long t, Converge cv) {
+__global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
+    AssignImage single, AssignTileMap map, long long t, Converge cv) {
     using Sh = Shape<VEC, ROWS>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_shift;
@@ -181,37 +214,51 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
     int bx, by;
     resolve_image(single, map, &g, &bx, &by);
     const size_t ring = static_cast<size_t>(g.K) * kSumStride;
-    long long* const sums_acc = g.sums + ring * static_cast<size_t>(t % 3);
-    const long long* const sums_prev =
-        t > 0 ? g.sums + ring * static_cast<size_t>((t + 2) % 3) : nullptr;
-    long long* const sums_next = g.sums + ring * static_cast<size_t>((t + 1) % 3);
+    gmem<long long>* const sums = as_global(g.sums);
+    gmem<long long>* const sums_acc = sums + ring * static_cast<size_t>(t % 3);
+    gmem<const long long>* const sums_prev =
+        t > 0 ? sums + ring * static_cast<size_t>((t + 2) % 3) : nullptr;
+    gmem<long long>* const sums_next = sums + ring * static_cast<size_t>((t + 1) % 3);
+    gmem<float>* const cen = as_global(g.cen);
+    gmem<int32_t>* const labels = as_global(g.labels);
     const int x0 = bx * Sh::kTileW, y0 = by * Sh::kTileH;
     const int tx = threadIdx.x % Sh::kTX, ty = threadIdx.x / Sh::kTX;
     const int x = x0 + tx * VEC;
     const bool col_ok = x < g.w;
 
-    // ---- prefetch this thread's pixels (they do not depend on the centres)
+    // ---- prefetch this thread's pixels (they do not depend on the centres).
+    // Every lane loads (pixels outside the image read a clamped position and
+    // are then zeroed), so the loads are issued unconditionally and the
+    // staging below overlaps them.
     float pl[ROWS][VEC], pa[ROWS][VEC], pb[ROWS][VEC];
+    {
+        gmem<const float>* const Lg = as_global(g.L);
+        gmem<const float>* const Ag = as_global(g.A);
+        gmem<const float>* const Bg = as_global(g.B);
+        const int xc = min(x, g.w - VEC);  // VEC = 4 needs width % 4 == 0
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int y = y0 + ty * ROWS + r;
-        if (col_ok && y < g.h) {
-            const size_t pi = static_cast<size_t>(y) * g.w + x;
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = y0 + ty * ROWS + r;
+            const bool in = col_ok && y < g.h;
+            const size_t pi = static_cast<size_t>(min(y, g.h - 1)) * g.w + xc;
             if constexpr (VEC == 4) {
-                const float4 l4 = *reinterpret_cast<const float4*>(g.L + pi);
-                const float4 a4 = *reinterpret_cast<const float4*>(g.A + pi);
-                const float4 b4 = *reinterpret_cast<const float4*>(g.B + pi);
+                const float4 l4 = load_f4(Lg + pi);
+                const float4 a4 = load_f4(Ag + pi);
+                const float4 b4 = load_f4(Bg + pi);
                 pl[r][0] = l4.x; pl[r][1] = l4.y; pl[r][2] = l4.z; pl[r][3] = l4.w;
                 pa[r][0] = a4.x; pa[r][1] = a4.y; pa[r][2] = a4.z; pa[r][3] = a4.w;
                 pb[r][0] = b4.x; pb[r][1] = b4.y; pb[r][2] = b4.z; pb[r][3] = b4.w;
             } else {
-                pl[r][0] = g.L[pi];
-                pa[r][0] = g.A[pi];
-                pb[r][0] = g.B[pi];
+                pl[r][0] = Lg[pi];
+                pa[r][0] = Ag[pi];
+                pb[r][0] = Bg[pi];
             }
-        } else {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) pl[r][v] = pa[r][v] = pb[r][v] = 0.0f;
+            for (int v = 0; v < VEC; ++v) {
+                pl[r][v] = in ? pl[r][v] : 0.0f;
+                pa[r][v] = in ? pa[r][v] : 0.0f;
+                pb[r][v] = in ? pb[r][v] : 0.0f;
+            }
         }
     }
 
@@ -223,8 +270,11 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
     float4* cen4 = reinterpret_cast<float4*>(smem);
     float* ceny = reinterpret_cast<float*>(cen4 + ncells);
     int* kidx = reinterpret_cast<int*>(ceny + ncells);
-    unsigned long long* bins = reinterpret_cast<unsigned long long*>(
-        reinterpret_cast<uintptr_t>(kidx + ncells + 1) & ~static_cast<uintptr_t>(7));
+    // 24 * ncells bytes precede the bins, a multiple of 8; offsets from smem
+    // keep the bins' LDS address space visible to the compiler, so their
+    // atomics are LDS atomics rather than flat ones
+    unsigned long long* bins =
+        reinterpret_cast<unsigned long long*>(smem + static_cast<size_t>(ncells) * 24);
 
     // ---- stage the candidate centres (and, from the second launch on,
     // derive them from the previous launch's sums)
@@ -241,46 +291,51 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         const int k = cy * g.ns_c + cx;
         kidx[i] = k;
         const bool owner = (cx * S) / Sh::kTileW == bx && (cy * S) / Sh::kTileH == by;
-        float* c = g.cen + static_cast<size_t>(k) * kCenStride;
-        float4 v;
-        float vy;
+        gmem<float>* c = cen + static_cast<size_t>(k) * kCenStride;
+        // every load first, so that one memory round trip serves them all
+        const float4 old4 = load_f4(c);  // the centre the previous launch used
+        const float oldy = c[4];
+        long long sv[kSumStride] = {};
         if (sums_prev) {
-            const long long* s = sums_prev + static_cast<size_t>(k) * kSumStride;
-            const long long n = s[5];
-            if (n > 0) {
-                const double dn = static_cast<double>(n);
-                const double inv = 1.0 / static_cast<double>(1 << kQShift);
-                const double ml = static_cast<double>(s[0]) / dn;
-                const double ma = static_cast<double>(s[1]) / dn;
-                const double mb = static_cast<double>(s[2]) / dn;
-                v = make_float4(static_cast<float>(ml * inv), static_cast<float>(ma * inv),
-                                static_cast<float>(mb * inv),
-                                static_cast<float>(static_cast<double>(s[3]) / dn));
-                vy = static_cast<float>(static_cast<double>(s[4]) / dn);
-                if (owner) {
-                    if (cv.ctl) {  // L1 shift, each component rint(|d| 2^18)
-                        const float4 o = *reinterpret_cast<const float4*>(c);
-                        const double q = static_cast<double>(1 << kQShift);
-                        my_shift += llrint(fabs(static_cast<double>(v.x) - o.x) * q) +
-                                    llrint(fabs(static_cast<double>(v.y) - o.y) * q) +
-                                    llrint(fabs(static_cast<double>(v.z) - o.z) * q) +
-                                    llrint(fabs(static_cast<double>(v.w) - o.w) * q) +
-                                    llrint(fabs(static_cast<double>(vy) - c[4]) * q);
-                    }
-                    *reinterpret_cast<float4*>(c) = v;
-                    c[4] = vy;
+            gmem<const long long>* sp = sums_prev + static_cast<size_t>(k) * kSumStride;
+#pragma unroll
+            for (int j = 0; j < kSumStride; ++j) sv[j] = sp[j];
+        }
+        float4 v = old4;
+        float vy = oldy;
+        if (sums_prev) {
+            // the means are computed unconditionally (and selected), so the
+            // sums' loads are not deferred behind a test of the count
+            const long long n = sv[5];
+            const double dn = static_cast<double>(n > 0 ? n : 1);
+            const double inv = 1.0 / static_cast<double>(1 << kQShift);
+            const double ml = static_cast<double>(sv[0]) / dn;
+            const double ma = static_cast<double>(sv[1]) / dn;
+            const double mb = static_cast<double>(sv[2]) / dn;
+            const float4 m4 = make_float4(static_cast<float>(ml * inv), static_cast<float>(ma * inv),
+                                          static_cast<float>(mb * inv),
+                                          static_cast<float>(static_cast<double>(sv[3]) / dn));
+            const float my = static_cast<float>(static_cast<double>(sv[4]) / dn);
+            const bool moved = n > 0;  // an empty cluster keeps its centre
+            v = make_float4(moved ? m4.x : old4.x, moved ? m4.y : old4.y, moved ? m4.z : old4.z,
+                            moved ? m4.w : old4.w);
+            vy = moved ? my : oldy;
+            if (owner && moved) {
+                if (cv.ctl) {  // L1 shift, each component rint(|d| 2^18)
+                    const double q = static_cast<double>(1 << kQShift);
+                    my_shift += llrint(fabs(static_cast<double>(v.x) - old4.x) * q) +
+                                llrint(fabs(static_cast<double>(v.y) - old4.y) * q) +
+                                llrint(fabs(static_cast<double>(v.z) - old4.z) * q) +
+                                llrint(fabs(static_cast<double>(v.w) - old4.w) * q) +
+                                llrint(fabs(static_cast<double>(vy) - oldy) * q);
                 }
-            } else {
-                v = *reinterpret_cast<const float4*>(c);
-                vy = c[4];
+                store_f4(c, v);
+                c[4] = vy;
             }
-            if (owner) g.counts[k] = static_cast<int32_t>(n);
-        } else {
-            v = *reinterpret_cast<const float4*>(c);
-            vy = c[4];
+            if (owner) as_global(g.counts)[k] = static_cast<int32_t>(n);
         }
         if (owner) {
-            long long* z = sums_next + static_cast<size_t>(k) * kSumStride;
+            gmem<long long>* z = sums_next + static_cast<size_t>(k) * kSumStride;
             for (int j = 0; j < kSumStride; ++j) z[j] = 0;
         }
         cen4[i] = v;
@@ -370,10 +425,10 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         if (!col_ok || y >= g.h) continue;
         const size_t pi = static_cast<size_t>(y) * g.w + x;
         if constexpr (VEC == 4) {
-            *reinterpret_cast<int4*>(g.labels + pi) =
-                make_int4(kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]], kidx[cellv[r][3]]);
+            store_i4(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]],
+                     kidx[cellv[r][3]]);
         } else {
-            g.labels[pi] = kidx[cellv[r][0]];
+            labels[pi] = kidx[cellv[r][0]];
         }
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -411,14 +466,14 @@ __global__ __launch_bounds__(kThreads) void assign_kernel(AssignImage single, As
         if (n == 0) continue;
         const long long sx = static_cast<long long>(p & 0xFFFFFull) + n * x0;
         const long long sy = static_cast<long long>((p >> 20) & 0xFFFFFull) + n * y0;
-        unsigned long long* s =
-            reinterpret_cast<unsigned long long*>(sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
-        atomicAdd(s + 0, bins[i]);
-        atomicAdd(s + 1, bins[ncells + i]);
-        atomicAdd(s + 2, bins[2 * ncells + i]);
-        atomicAdd(s + 3, static_cast<unsigned long long>(sx));
-        atomicAdd(s + 4, static_cast<unsigned long long>(sy));
-        atomicAdd(s + 5, static_cast<unsigned long long>(n));
+        gmem<unsigned long long>* s = reinterpret_cast<gmem<unsigned long long>*>(
+            sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
+        const unsigned long long add[kSumStride] = {
+            bins[i], bins[ncells + i], bins[2 * ncells + i], static_cast<unsigned long long>(sx),
+            static_cast<unsigned long long>(sy), static_cast<unsigned long long>(n)};
+#pragma unroll
+        for (int j = 0; j < kSumStride; ++j)
+            __hip_atomic_fetch_add(s + j, add[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -216,37 +216,93 @@ __device__ __forceinline__ int find_halving(int* P, int x) {
 // the smallest indices of their trees and are exactly the components that
 // are not small (or hold pixel 0).  Each small root links itself under the
 // current root of its target (only its own thread links comp[r]; path
-// halving later shortens links, always to ancestors with smaller indices);
-// the tree roots are then found by path-halving finds in the relabel pass.  The workgroup numbers its
-// surviving roots (ballot prefix counts) and stores their count.
-constexpr int kMergeBlock = 1024;
+// halving shortens links, always to ancestors with smaller indices) and
+// marks itself with rank -1; the workgroup numbers its surviving roots in
+// raster order (ballot prefix counts) and stores their count.
+//
+// A workgroup covers kMergeBlock consecutive pixels; thread t handles pixels
+// t, t + kBlock, ... of them, so every load of the pass is coalesced and each
+// thread has kMergePx independent loads in flight.  The root test reads comp
+// without synchronisation while other threads link and shorten paths: a
+// root's own entry is changed only by its own thread, after the test, and
+// every other entry holds a smaller index at all times, so a stale value
+// cannot change the outcome.
+constexpr int kMergePx = 4;
+constexpr int kMergeBlock = kBlock * kMergePx;
 
-__global__ __launch_bounds__(kMergeBlock) void ccl_merge_kernel(
+__global__ __launch_bounds__(kBlock) void ccl_merge_kernel(
     int n, int w, long long S2, int min_segment, int* comp, const int* __restrict__ size,
     int* __restrict__ rank, int* __restrict__ block_count) {
-    __shared__ int wave_total[kMergeBlock / 64];
-    const int r = blockIdx.x * kMergeBlock + threadIdx.x;
-    bool survives = false;
-    if (r < n && load_relaxed(comp + r) == r) {
-        const int sz = size[r];
-        const bool small = min_segment > 0 ? sz < min_segment : 4ll * sz < S2;
-        if (r == 0 || !small) {
-            survives = true;
-        } else {
-            const int t = find_halving(comp, (r % w) > 0 ? r - 1 : r - w);
-            __hip_atomic_store(comp + r, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ int part[kMergePx * (kBlock / 64)];
+    const int base = blockIdx.x * kMergeBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool root[kMergePx];
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        const int r = base + j * kBlock;
+        root[j] = r < n && comp[r] == r;
+    }
+    int sz[kMergePx];
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) sz[j] = root[j] ? size[base + j * kBlock] : 0;
+    bool survives[kMergePx];
+    int x[kMergePx];          // join walks: the node each one stands on
+    unsigned walking = 0u;    // bit j: pixel j is a small root looking for its target
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        const int r = base + j * kBlock;
+        const bool small = min_segment > 0 ? sz[j] < min_segment : 4ll * sz[j] < S2;
+        survives[j] = root[j] && (r == 0 || !small);
+        x[j] = (r % w) > 0 ? r - 1 : r - w;
+        if (root[j] && !survives[j]) walking |= 1u << j;
+    }
+    // Path-halving finds from the pixel left of (or above) each small root,
+    // the thread's walks advanced together so that their loads overlap: a
+    // step reads the node's parent p and grandparent gp, re-links the node
+    // to gp (an ancestor, so concurrent walks stay correct) and moves to gp.
+    for (unsigned live = walking; live;) {
+        int p[kMergePx], gp[kMergePx];
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j)
+            if (live & (1u << j)) p[j] = load_relaxed(comp + x[j]);
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j)
+            if ((live & (1u << j)) && p[j] == x[j]) live &= ~(1u << j);
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j)
+            if (live & (1u << j)) gp[j] = load_relaxed(comp + p[j]);
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j) {
+            if (!(live & (1u << j))) continue;
+            if (gp[j] != p[j])
+                __hip_atomic_store(comp + x[j], gp[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            x[j] = gp[j];
         }
     }
-    const unsigned long long ballot = __ballot(survives);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) wave_total[wave] = __popcll(ballot);
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        if (!(walking & (1u << j))) continue;
+        const int r = base + j * kBlock;
+        __hip_atomic_store(comp + r, x[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rank[r] = -1;
+    }
+    unsigned long long ballot[kMergePx];
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        ballot[j] = __ballot(survives[j]);
+        if (lane == 0) part[j * (kBlock / 64) + wave] = __popcll(ballot[j]);
+    }
     __syncthreads();
-    int offset = 0;
-    for (int j = 0; j < wave; ++j) offset += wave_total[j];
-    if (survives) rank[r] = offset + __popcll(ballot & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        if (!survives[j]) continue;
+        int offset = 0;  // survivors in the (pass, wave) groups before this one
+        for (int q = 0; q < j * (kBlock / 64) + wave; ++q) offset += part[q];
+        rank[base + j * kBlock] = offset + __popcll(ballot[j] & ((1ull << lane) - 1ull));
+    }
     if (threadIdx.x == 0) {
         int total = 0;
-        for (int j = 0; j < kMergeBlock / 64; ++j) total += wave_total[j];
+        for (int q = 0; q < kMergePx * (kBlock / 64); ++q) total += part[q];
         block_count[blockIdx.x] = total;
     }
 }
@@ -277,15 +333,49 @@ __global__ __launch_bounds__(kBlock) void ccl_scan_kernel(int nblocks, int* __re
     if (threadIdx.x == kBlock - 1 && n_segments) *n_segments = part[kBlock - 1];
 }
 
-// Final labels: rank of the pixel's surviving root.
-__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int* comp,
+// Final labels: rank of the pixel's surviving root.  Every entry of comp
+// holds some component's root; a surviving root carries its rank, a joined
+// one -1, after which the join links are followed to the tree root.  Nothing
+// writes comp in this pass.  Same pixel-to-thread map as the merge pass.
+__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, const int* __restrict__ comp,
                                                              const int* __restrict__ rank,
                                                              const int* __restrict__ block_off,
                                                              int32_t* __restrict__ out) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int f = find_halving(comp, i);
-    out[i] = rank[f] + block_off[f / kMergeBlock];
+    const int base = blockIdx.x * kMergeBlock + threadIdx.x;
+    int r[kMergePx], k[kMergePx], o[kMergePx];
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        const int i = base + j * kBlock;
+        r[j] = i < n ? comp[i] : 0;  // pixel 0 is always a surviving root
+    }
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        k[j] = rank[r[j]];
+        o[j] = block_off[r[j] / kMergeBlock];
+    }
+    // joined roots: follow the links (to smaller roots) until a surviving
+    // one; the thread's walks advance together so their loads overlap
+    unsigned live = 0u;
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j)
+        if (k[j] < 0) live |= 1u << j;
+    while (live) {
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j)
+            if (live & (1u << j)) r[j] = comp[r[j]];
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j) {
+            if (!(live & (1u << j))) continue;
+            k[j] = rank[r[j]];
+            o[j] = block_off[r[j] / kMergeBlock];
+            if (k[j] >= 0) live &= ~(1u << j);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        const int i = base + j * kBlock;
+        if (i < n) out[i] = k[j] + o[j];
+    }
 }
 
 }  // namespace
@@ -296,7 +386,6 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
                                hipStream_t s) {
     const int n = w * h;
-    const int nb = (n + kBlock - 1) / kBlock;
     int* comp = ws.ccl0;  // local roots, then component roots, then join links
     int* size = ws.ccl1;  // component sizes
     int* rank = ws.ccl2;  // ranks of the surviving roots
@@ -316,12 +405,12 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
     SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(w, h, comp, lroot, size));
     const int nmerge = scan_tiles_for(n);
     SLIC_STEP("ccl_merge",
-              ccl_merge_kernel<<<nmerge, kMergeBlock, 0, s>>>(
+              ccl_merge_kernel<<<nmerge, kBlock, 0, s>>>(
                   n, w, static_cast<long long>(g.S) * g.S, min_segment, comp, size, rank,
                   block_count));
     SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(nmerge, block_count, n_segments));
     SLIC_STEP("ccl_relabel",
-              ccl_relabel_kernel<<<nb, kBlock, 0, s>>>(n, comp, rank, block_count, labels_out));
+              ccl_relabel_kernel<<<nmerge, kBlock, 0, s>>>(n, comp, rank, block_count, labels_out));
 #undef SLIC_STEP
     return hipSuccess;
 }
