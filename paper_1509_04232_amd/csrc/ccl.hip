@@ -13,8 +13,10 @@
 // GPU structure: concurrent union-find whose links always point from a
 // larger to a smaller index (so a tree's root is its minimum), first inside
 // 32 x 32 tiles in LDS, then across tile borders in global memory; the joins
-// of step 3 are links in the same union-find; ballot counts and a
-// one-workgroup prefix sum over the surviving roots for the numbering.  All integer, so the result is exact.
+// of step 3 recorded per small root as links in the rank array and followed
+// (with path splitting) by the relabel pass; ballot counts and prefix sums
+// over the surviving roots for the numbering.  All integer, so the result
+// is exact.
 #include "slic_internal.h"
 
 namespace slic {
@@ -197,94 +199,48 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int w, int h, int* 
     }
 }
 
-// Find with path halving: every visited node is re-linked to its
-// grandparent (still an ancestor, so concurrent finds stay correct).
-__device__ __forceinline__ int find_halving(int* P, int x) {
-    int p = load_relaxed(P + x);
-    while (p != x) {
-        const int gp = load_relaxed(P + p);
-        if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        x = gp;
-        p = load_relaxed(P + x);
-    }
-    return x;
-}
-
 // Joins.  A small component (other than the one holding pixel 0) joins the
 // component of the pixel left of its root r, or above r at a row start;
 // both have smaller roots, so the joins form a forest whose tree roots are
 // the smallest indices of their trees and are exactly the components that
-// are not small (or hold pixel 0).  Each small root links itself under the
-// current root of its target (only its own thread links comp[r]; path
-// halving shortens links, always to ancestors with smaller indices) and
-// marks itself with rank -1; the workgroup numbers its surviving roots in
-// raster order (ballot prefix counts) and stores their count.
+// are not small (or hold pixel 0).  After the flatten pass every entry of
+// comp holds its pixel's component root and nothing writes comp any more, so
+// a small root records its join target directly as rank[r] = -2 - comp[q]
+// (q the pixel left of or above r); a surviving root gets its rank in raster
+// order among the workgroup's survivors (ballot prefix counts), and the
+// workgroup stores their count.
 //
 // A workgroup covers kMergeBlock consecutive pixels; thread t handles pixels
-// t, t + kBlock, ... of them, so every load of the pass is coalesced and each
-// thread has kMergePx independent loads in flight.  The root test reads comp
-// without synchronisation while other threads link and shorten paths: a
-// root's own entry is changed only by its own thread, after the test, and
-// every other entry holds a smaller index at all times, so a stale value
-// cannot change the outcome.
+// t, t + kBlock, ... of them, so every load of the pass is coalesced.  Loads
+// are unconditional (positions past the image are clamped) so that a
+// thread's loads are issued together rather than one branch at a time.
 constexpr int kMergePx = 4;
 constexpr int kMergeBlock = kBlock * kMergePx;
 
 __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(
-    int n, int w, long long S2, int min_segment, int* comp, const int* __restrict__ size,
-    int* __restrict__ rank, int* __restrict__ block_count) {
+    int n, int w, long long S2, int min_segment, const int* __restrict__ comp,
+    const int* __restrict__ size, int* __restrict__ rank, int* __restrict__ block_count) {
     __shared__ int part[kMergePx * (kBlock / 64)];
     const int base = blockIdx.x * kMergeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool root[kMergePx];
+    int sz[kMergePx], tgt[kMergePx];
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) {
         const int r = base + j * kBlock;
-        root[j] = r < n && comp[r] == r;
+        const int rc = min(r, n - 1);
+        root[j] = r < n && comp[rc] == r;
+        sz[j] = size[rc];
+        const int q = rc % w > 0 ? rc - 1 : rc - w;  // left of r, or above it
+        tgt[j] = comp[max(q, 0)];
     }
-    int sz[kMergePx];
-#pragma unroll
-    for (int j = 0; j < kMergePx; ++j) sz[j] = root[j] ? size[base + j * kBlock] : 0;
     bool survives[kMergePx];
-    int x[kMergePx];          // join walks: the node each one stands on
-    unsigned walking = 0u;    // bit j: pixel j is a small root looking for its target
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) {
         const int r = base + j * kBlock;
         const bool small = min_segment > 0 ? sz[j] < min_segment : 4ll * sz[j] < S2;
         survives[j] = root[j] && (r == 0 || !small);
-        x[j] = (r % w) > 0 ? r - 1 : r - w;
-        if (root[j] && !survives[j]) walking |= 1u << j;
-    }
-    // Path-halving finds from the pixel left of (or above) each small root,
-    // the thread's walks advanced together so that their loads overlap: a
-    // step reads the node's parent p and grandparent gp, re-links the node
-    // to gp (an ancestor, so concurrent walks stay correct) and moves to gp.
-    for (unsigned live = walking; live;) {
-        int p[kMergePx], gp[kMergePx];
-#pragma unroll
-        for (int j = 0; j < kMergePx; ++j)
-            if (live & (1u << j)) p[j] = load_relaxed(comp + x[j]);
-#pragma unroll
-        for (int j = 0; j < kMergePx; ++j)
-            if ((live & (1u << j)) && p[j] == x[j]) live &= ~(1u << j);
-#pragma unroll
-        for (int j = 0; j < kMergePx; ++j)
-            if (live & (1u << j)) gp[j] = load_relaxed(comp + p[j]);
-#pragma unroll
-        for (int j = 0; j < kMergePx; ++j) {
-            if (!(live & (1u << j))) continue;
-            if (gp[j] != p[j])
-                __hip_atomic_store(comp + x[j], gp[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            x[j] = gp[j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kMergePx; ++j) {
-        if (!(walking & (1u << j))) continue;
-        const int r = base + j * kBlock;
-        __hip_atomic_store(comp + r, x[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        rank[r] = -1;
+        if (root[j] && !survives[j]) rank[r] = -2 - tgt[j];
     }
     unsigned long long ballot[kMergePx];
 #pragma unroll
@@ -333,48 +289,116 @@ __global__ __launch_bounds__(kBlock) void ccl_scan_kernel(int nblocks, int* __re
     if (threadIdx.x == kBlock - 1 && n_segments) *n_segments = part[kBlock - 1];
 }
 
-// Final labels: rank of the pixel's surviving root.  Every entry of comp
-// holds some component's root; a surviving root carries its rank, a joined
-// one -1, after which the join links are followed to the tree root.  Nothing
-// writes comp in this pass.  Same pixel-to-thread map as the merge pass.
-__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, const int* __restrict__ comp,
-                                                             const int* __restrict__ rank,
-                                                             const int* __restrict__ block_off,
-                                                             int32_t* __restrict__ out) {
+// Up to this many merge workgroups every relabel workgroup scans the
+// per-workgroup survivor counts itself, in LDS, and the one-workgroup scan
+// launch is skipped; beyond it the scan kernel runs first.
+constexpr int kFusedScanMax = 4096;
+
+// Final labels: rank of the pixel's surviving root plus the number of
+// survivors in earlier merge workgroups.  comp[i] is the pixel's component
+// root; a surviving root carries its rank, a joined one -2 - (the root it
+// joins), and the joins are followed to the tree root.  Same pixel-to-thread
+// map as the merge pass.  With kScan, block_count holds the merge pass's
+// counts and every workgroup derives the offsets itself (workgroup 0 also
+// stores the total); otherwise it holds the offsets already.
+template <bool kScan>
+__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int nblocks,
+                                                             const int* __restrict__ comp,
+                                                             int* rank,
+                                                             const int* __restrict__ block_count,
+                                                             int32_t* __restrict__ out,
+                                                             int32_t* __restrict__ n_segments) {
+    extern __shared__ int s_off[];  // kScan: nblocks offsets
+    __shared__ int wave_part[kBlock / 64];
     const int base = blockIdx.x * kMergeBlock + threadIdx.x;
-    int r[kMergePx], k[kMergePx], o[kMergePx];
+    int r[kMergePx], k[kMergePx];
 #pragma unroll
-    for (int j = 0; j < kMergePx; ++j) {
-        const int i = base + j * kBlock;
-        r[j] = i < n ? comp[i] : 0;  // pixel 0 is always a surviving root
-    }
+    for (int j = 0; j < kMergePx; ++j)  // clamped: loads issued together
+        r[j] = comp[min(base + j * kBlock, n - 1)];
 #pragma unroll
-    for (int j = 0; j < kMergePx; ++j) {
-        k[j] = rank[r[j]];
-        o[j] = block_off[r[j] / kMergeBlock];
+    for (int j = 0; j < kMergePx; ++j) k[j] = rank[r[j]];
+    if constexpr (kScan) {
+        // exclusive prefix sums of the counts into s_off: coalesced loads
+        // into LDS, each thread sums a run of consecutive counts, the runs'
+        // sums are scanned with shuffles in each wavefront and then across
+        // the wavefronts, and each thread writes its run's offsets back
+        constexpr int kQ = kFusedScanMax / kBlock;
+        int cnt[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)  // clamped, so every load is issued at once
+            cnt[q] = block_count[min(static_cast<int>(threadIdx.x) + q * kBlock, nblocks - 1)];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int j = threadIdx.x + q * kBlock;
+            if (j < nblocks) s_off[j] = cnt[q];
+        }
+        __syncthreads();
+        const int per = (nblocks + kBlock - 1) / kBlock;
+        const int lo = min(static_cast<int>(threadIdx.x) * per, nblocks);
+        const int hi = min(lo + per, nblocks);
+        int sum = 0;
+        for (int j = lo; j < hi; ++j) sum += s_off[j];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        int inc = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(inc, d);
+            if (lane >= d) inc += v;
+        }
+        if (lane == 63) wave_part[wave] = inc;
+        __syncthreads();
+        int run = inc - sum, total = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            if (q < wave) run += wave_part[q];
+            total += wave_part[q];
+        }
+        for (int j = lo; j < hi; ++j) {
+            const int c = s_off[j];
+            s_off[j] = run;
+            run += c;
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x == 0 && n_segments) *n_segments = total;
     }
-    // joined roots: follow the links (to smaller roots) until a surviving
-    // one; the thread's walks advance together so their loads overlap
+    // Follow the joins to a surviving root, one rank load per step, the
+    // thread's walks advanced together (finished ones reload their root,
+    // harmlessly) so that their loads overlap.  Each step also re-links the
+    // root visited before to the current root's target (path splitting: the
+    // target is an ancestor, so concurrent walks stay correct), so walks
+    // that pass the same chain of joins later find it shorter.
+    int prev[kMergePx];
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) prev[j] = -1;
     unsigned live = 0u;
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j)
         if (k[j] < 0) live |= 1u << j;
     while (live) {
+        int nx[kMergePx], kn[kMergePx];
 #pragma unroll
-        for (int j = 0; j < kMergePx; ++j)
-            if (live & (1u << j)) r[j] = comp[r[j]];
+        for (int j = 0; j < kMergePx; ++j) nx[j] = k[j] < 0 ? -2 - k[j] : r[j];
+#pragma unroll
+        for (int j = 0; j < kMergePx; ++j) kn[j] = rank[nx[j]];
 #pragma unroll
         for (int j = 0; j < kMergePx; ++j) {
             if (!(live & (1u << j))) continue;
-            k[j] = rank[r[j]];
-            o[j] = block_off[r[j] / kMergeBlock];
+            if (prev[j] >= 0) rank[prev[j]] = k[j];
+            prev[j] = r[j];
+            r[j] = nx[j];
+            k[j] = kn[j];
             if (k[j] >= 0) live &= ~(1u << j);
         }
     }
+    auto offset_of = [&](int root) {
+        if constexpr (kScan) {
+            return s_off[root / kMergeBlock];
+        } else {
+            return block_count[root / kMergeBlock];
+        }
+    };
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) {
         const int i = base + j * kBlock;
-        if (i < n) out[i] = k[j] + o[j];
+        if (i < n) out[i] = k[j] + offset_of(r[j]);
     }
 }
 
@@ -408,9 +432,17 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
               ccl_merge_kernel<<<nmerge, kBlock, 0, s>>>(
                   n, w, static_cast<long long>(g.S) * g.S, min_segment, comp, size, rank,
                   block_count));
-    SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(nmerge, block_count, n_segments));
-    SLIC_STEP("ccl_relabel",
-              ccl_relabel_kernel<<<nmerge, kBlock, 0, s>>>(n, comp, rank, block_count, labels_out));
+    if (nmerge <= kFusedScanMax) {
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<true><<<nmerge, kBlock, nmerge * sizeof(int), s>>>(
+                      n, nmerge, comp, rank, block_count, labels_out, n_segments));
+    } else {
+        SLIC_STEP("ccl_scan",
+                  ccl_scan_kernel<<<1, kBlock, 0, s>>>(nmerge, block_count, n_segments));
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<false><<<nmerge, kBlock, 0, s>>>(
+                      n, nmerge, comp, rank, block_count, labels_out, nullptr));
+    }
 #undef SLIC_STEP
     return hipSuccess;
 }

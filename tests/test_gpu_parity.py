@@ -125,6 +125,18 @@ def test_edge_shapes(slic, w, h, S, K):
     assert_parity(got, want, enforce=True)
 
 
+@pytest.mark.parametrize("w,h", [(2048, 2048), (2560, 1700)])
+def test_connectivity_numbering_both_scan_paths(slic, w, h):
+    """The segment numbering sums per-workgroup survivor counts (1024 pixels
+    per workgroup): inside the relabel pass up to 4096 workgroups
+    (4,194,304 pixels, the first case exactly), with a separate scan launch
+    beyond that (the second case, 4,352,000 pixels)."""
+    img = synth.voronoi_image(w + h, w, h, 400, 8.0)
+    got = gpu_run(slic, img, 32, 10.0, 1, True, enforce=True)
+    want = oracle_run(img, 32, 10.0, 1, True, enforce=True)
+    assert_parity(got, want, enforce=True)
+
+
 @pytest.mark.parametrize("w,h,S", [(64, 48, 16), (40, 24, 8), (96, 96, 3)])
 def test_uniform_image_closed_form(slic, w, h, S):
     img = np.full((h, w, 3), (90, 140, 200), np.uint8)
@@ -255,9 +267,12 @@ def test_autotune_records_a_supported_variant(slic):
     rgb, _ = _to_dev(img)
     p = slic.Params(wl.width, wl.height, S=wl.S, m=wl.m)
     ws = slic.workspace_for(p)
+    # listing the supported variants sets and then clears the recorded
+    # choice, so it comes before the autotuner records one
+    supported = _supported_variants(slic, wl.width, wl.height, wl.S)
     try:
         best, ms = slic.slic_autotune(p.c(), rgb.data_ptr(), 3, 2, 0, ws.data_ptr(), ws.numel())
-        assert best in _supported_variants(slic, wl.width, wl.height, wl.S) or best >= 1
+        assert best in supported
         assert ms > 0
         assert slic.slic_get_assign_variant(wl.width, wl.height, wl.S) == best
         got = gpu_run(slic, img, wl.S, wl.m, wl.iters, wl.perturb)
