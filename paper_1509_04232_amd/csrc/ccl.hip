@@ -28,13 +28,16 @@ __device__ __forceinline__ int load_relaxed(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int find_root(int* P, int x) {
-    int p = load_relaxed(P + x);
-    while (p != x) {
-        x = p;
-        p = load_relaxed(P + x);
+// The roots of a and b, the two walks advanced together so that their
+// loads overlap.
+__device__ __forceinline__ void find_roots(int* P, int& a, int& b) {
+    int pa = load_relaxed(P + a), pb = load_relaxed(P + b);
+    while (pa != a || pb != b) {
+        a = pa;
+        b = pb;
+        pa = load_relaxed(P + a);
+        pb = load_relaxed(P + b);
     }
-    return x;
 }
 
 // Merge the trees of a and b, linking the larger root under the smaller.
@@ -43,8 +46,7 @@ __device__ __forceinline__ int find_root(int* P, int x) {
 __device__ void unite(int* P, int a, int b) {
     bool done;
     do {
-        a = find_root(P, a);
-        b = find_root(P, b);
+        find_roots(P, a, b);
         if (a < b) {
             const int old = atomicMin(P + b, a);
             done = old == b;
@@ -113,10 +115,18 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(const int32_t* __rest
     __shared__ int par[kTilePx];
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
     const int col = threadIdx.x % kTile;
+    int v[kPxPerThread];
+#pragma unroll
+    for (int j = 0; j < kPxPerThread; ++j) {  // clamped: the loads are issued together
+        const int li = threadIdx.x + j * kBlock;
+        const int x = x0 + col, y = y0 + li / kTile;
+        v[j] = labels[static_cast<size_t>(min(y, h - 1)) * w + min(x, w - 1)];
+    }
+#pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
         const int x = x0 + col, y = y0 + li / kTile;
-        lab[li] = (x < w && y < h) ? labels[static_cast<size_t>(y) * w + x] : -1;
+        lab[li] = (x < w && y < h) ? v[j] : -1;
     }
     __syncthreads();
     // every pixel links to the head (first pixel) of its run
@@ -171,27 +181,60 @@ __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(const int32_t* __
 }
 
 // comp[i] = P[i] = root of i (the component's smallest index); the tile adds
-// its pixel count per local root to size[root].
+// its pixel count per local root to size[root].  Only the tile's local roots
+// walk the forest (the thread's walks advanced together, with unconditional
+// loads, so that they overlap); every pixel then takes its local root's
+// result from LDS.
 __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int w, int h, int* P,
                                                              const int* __restrict__ lroot,
                                                              int* __restrict__ size) {
     __shared__ int cnt[kTilePx];
     __shared__ int root[kTilePx];
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-    for (int j = 0; j < kPxPerThread; ++j) cnt[threadIdx.x + j * kBlock] = 0;
-    __syncthreads();
+    int lr[kPxPerThread], x[kPxPerThread];
+    bool in[kPxPerThread];
+#pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + li % kTile, y = y0 + li / kTile;
-        if (x >= w || y >= h) continue;
-        const size_t gi = static_cast<size_t>(y) * w + x;
-        const int lr = lroot[gi];
-        const int r = find_root(P, (y0 + lr / kTile) * w + x0 + lr % kTile);
-        atomicAdd(cnt + lr, 1);
-        root[lr] = r;
-        __hip_atomic_store(P + gi, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int px = x0 + li % kTile, py = y0 + li / kTile;
+        in[j] = px < w && py < h;
+        lr[j] = lroot[static_cast<size_t>(min(py, h - 1)) * w + min(px, w - 1)];
+        cnt[li] = 0;
+        // a local root starts a walk from its own pixel; others stand on
+        // pixel 0, which is always a root
+        x[j] = in[j] && lr[j] == li ? py * w + px : 0;
+    }
+    unsigned live = 0u;
+#pragma unroll
+    for (int j = 0; j < kPxPerThread; ++j)
+        if (x[j] != 0) live |= 1u << j;
+    while (live) {
+        int p[kPxPerThread];
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) p[j] = load_relaxed(P + x[j]);
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) {
+            if (!(live & (1u << j))) continue;
+            if (p[j] == x[j]) live &= ~(1u << j);
+            x[j] = p[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kPxPerThread; ++j) {
+        const int li = threadIdx.x + j * kBlock;
+        if (in[j] && lr[j] == li) root[li] = x[j];
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPxPerThread; ++j) {
+        if (!in[j]) continue;
+        const int li = threadIdx.x + j * kBlock;
+        atomicAdd(cnt + lr[j], 1);
+        const size_t gi = static_cast<size_t>(y0 + li / kTile) * w + x0 + li % kTile;
+        __hip_atomic_store(P + gi, root[lr[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+#pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
         const int c = cnt[li];
