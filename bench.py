@@ -201,6 +201,34 @@ def bench_c4(slic, torch, dev, reps: int):
             "assign_hbm_frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
+def bench_c2_batched(slic, torch, dev, n_frames: int, reps: int):
+    """c2-sized frames (each its own seeded image) segmented together through
+    one batch plan with connectivity: every launch covers all frames, so the
+    small-launch latency of a single 640x480 frame is shared.  Frames/s of
+    the batch, beside the sequential rate of the headline."""
+    import dataclasses
+
+    import synth
+    base = synth.WORKLOADS["c2"]
+    wls = [dataclasses.replace(base, seed=base.seed + 1000 + j) for j in range(n_frames)]
+    imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in wls]
+    params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb,
+                          min_segment=w.min_segment) for w in wls]
+    b = slic.Batch(params, imgs, base.iters, enforce=True, use_graph=True)
+    variant, _ = b.autotune(reps=2)
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    b.close()
+    return {"frames": n_frames, "variant": variant, "ms_per_batch": round(t * 1e3, 3),
+            "frames_per_s": round(n_frames / t, 1)}
+
+
 def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps: int,
              hd: bool = False):
     """Workload c5: the learned warm start.  Trains the net on the GPU (crops
@@ -578,6 +606,7 @@ def main() -> int:
                     "assign_variant": fq.variant}
             extra[name] = entry
         extra["c4"] = bench_c4(slic, torch, dev, reps=max(5, args.steps // 50))
+        extra["c2_batched"] = bench_c2_batched(slic, torch, dev, 16, reps=max(5, args.steps // 50))
         extra["c5"] = bench_c5(slic, torch, dev, args.train_steps, args.train_images, 32,
                                reps=max(3, args.steps // 100))
         extra["video"] = bench_video(slic, torch, dev, 32, 2, reps=max(3, args.steps // 100))
