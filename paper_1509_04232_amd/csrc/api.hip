@@ -240,6 +240,13 @@ struct slic_batch {
     int* asg_tile_image = nullptr;
     int* asg_tile_first = nullptr;
     int asg_tiles = 0, asg_tiles_cap = 0;
+    slic::CclImage* ccl_images = nullptr;
+    int* ccl_tile_image = nullptr;
+    int* ccl_tile_first = nullptr;
+    int* ccl_blk_image = nullptr;
+    int* ccl_blk_first = nullptr;
+    int ccl_tiles = 0, ccl_blocks = 0, ccl_max_nmerge = 0;
+    int ccl_batched = 0;  // every image fits the batched connectivity launches
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int state = 0;  // 0 ok, 2 poisoned
@@ -263,8 +270,10 @@ size_t batch_layout(const slic_params* p, int32_t n, slic_batch* b, char* base) 
         off += align_up(bytes);
         return q;
     };
-    int lab_tiles = 0, asg_cap = 0;
+    int lab_tiles = 0, asg_cap = 0, ccl_tiles = 0, ccl_blocks = 0;
     for (int i = 0; i < n; ++i) {
+        ccl_tiles += ccl_tiles_for(p[i].width, p[i].height);
+        ccl_blocks += scan_tiles_for(p[i].width * p[i].height);
         Grid g;
         compute_grid(p + i, &g);
         Workspace w{};
@@ -291,7 +300,17 @@ size_t batch_layout(const slic_params* p, int32_t n, slic_batch* b, char* base) 
     char* ai = take(sizeof(AssignImage) * n);
     char* at = take(sizeof(int) * asg_cap);
     char* af = take(sizeof(int) * n);
+    char* ci = take(sizeof(CclImage) * n);
+    char* ct = take(sizeof(int) * ccl_tiles);
+    char* cf = take(sizeof(int) * n);
+    char* cb = take(sizeof(int) * ccl_blocks);
+    char* cbf = take(sizeof(int) * n);
     if (b) {
+        b->ccl_images = reinterpret_cast<CclImage*>(ci);
+        b->ccl_tile_image = reinterpret_cast<int*>(ct);
+        b->ccl_tile_first = reinterpret_cast<int*>(cf);
+        b->ccl_blk_image = reinterpret_cast<int*>(cb);
+        b->ccl_blk_first = reinterpret_cast<int*>(cbf);
         b->lab_images = reinterpret_cast<LabSeedImage*>(li);
         b->lab_tile_image = reinterpret_cast<int*>(lt);
         b->lab_tile_first = reinterpret_cast<int*>(lf);
@@ -348,14 +367,55 @@ hipError_t batch_upload_lab(slic_batch* b) {
     return e;
 }
 
+// Connectivity tables: every image's descriptor and the maps from
+// workgroups to (image, tile) and (image, run of 1024 pixels).
+hipError_t batch_upload_ccl(slic_batch* b) {
+    std::vector<CclImage> imgs(b->n);
+    std::vector<int> tfirst(b->n), bfirst(b->n), tile_image, blk_image;
+    b->ccl_batched = 1;
+    b->ccl_max_nmerge = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const slic_params& p = b->params[i];
+        imgs[i] = ccl_image(b->ws[i], p.width, p.height, b->grids[i], p.min_segment, b->labels[i],
+                            b->n_segments ? b->n_segments + i : nullptr);
+        if (!ccl_batch_supported(p.width, p.height)) b->ccl_batched = 0;
+        b->ccl_max_nmerge = std::max(b->ccl_max_nmerge, imgs[i].nmerge);
+        tfirst[i] = static_cast<int>(tile_image.size());
+        tile_image.insert(tile_image.end(), static_cast<size_t>(ccl_tiles_for(p.width, p.height)), i);
+        bfirst[i] = static_cast<int>(blk_image.size());
+        blk_image.insert(blk_image.end(), static_cast<size_t>(imgs[i].nmerge), i);
+    }
+    b->ccl_tiles = static_cast<int>(tile_image.size());
+    b->ccl_blocks = static_cast<int>(blk_image.size());
+    hipError_t e = hipMemcpy(b->ccl_images, imgs.data(), sizeof(CclImage) * b->n,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ccl_tile_image, tile_image.data(), sizeof(int) * tile_image.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ccl_tile_first, tfirst.data(), sizeof(int) * b->n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ccl_blk_image, blk_image.data(), sizeof(int) * blk_image.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ccl_blk_first, bfirst.data(), sizeof(int) * b->n, hipMemcpyHostToDevice);
+    return e;
+}
+
 // The whole pipeline for every image: one conversion+seeding launch,
-// 1 + n_iters association launches, then connectivity per image.
+// 1 + n_iters association launches, then the connectivity passes (each one
+// launch over every image when all of them fit the batched passes).
 hipError_t batch_enqueue(const slic_batch* b, hipStream_t s) {
     const LabSeedTileMap lmap{b->lab_images, b->lab_tile_image, b->lab_tile_first};
     hipError_t e = launch_lab_seed_batch(lmap, b->lab_tiles, s);
     const AssignTileMap amap{b->asg_images, b->asg_tile_image, b->asg_tile_first};
     for (int t = 0; e == hipSuccess && t <= b->n_iters; ++t)
         e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, b->grids[0].dist, s);
+    if (e == hipSuccess && b->enforce && b->ccl_batched) {
+        const CclMap cmap{b->ccl_images, b->ccl_tile_image, b->ccl_tile_first, b->ccl_blk_image,
+                          b->ccl_blk_first};
+        return launch_connectivity_batch(cmap, b->ccl_tiles, b->ccl_blocks, b->ccl_max_nmerge, s);
+    }
     for (int i = 0; e == hipSuccess && b->enforce && i < b->n; ++i) {
         Workspace w = b->ws[i];
         w.labels = b->labels[i];
@@ -808,6 +868,7 @@ int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_
     }
     hipError_t e = batch_upload_lab(b);
     if (e == hipSuccess) e = batch_upload_assign(b, variant);
+    if (e == hipSuccess) e = batch_upload_ccl(b);
     if (e == hipSuccess && b->use_graph) e = batch_capture(b);
     if (e != hipSuccess) {
         batch_drop_graph(b);

@@ -68,6 +68,37 @@ constexpr int kTile = 32;
 constexpr int kTilePx = kTile * kTile;
 constexpr int kPxPerThread = kTilePx / kBlock;
 
+// A workgroup's image and its tile (x, y) among the image's 32 x 32 tiles:
+// from the kernel argument and the launch grid (one image) or, for a batch,
+// from the image table through the tile-to-image map.
+__device__ __forceinline__ void resolve_tile(const CclImage& single, const CclMap& map,
+                                             CclImage* g, int* bx, int* by) {
+    if (map.images) {
+        const int img = map.tile_image[blockIdx.x];
+        *g = map.images[img];
+        const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
+        *bx = local % g->tiles_x;
+        *by = local / g->tiles_x;
+    } else {
+        *g = single;
+        *bx = blockIdx.x;
+        *by = blockIdx.y;
+    }
+}
+
+// Likewise for the passes over runs of kMergeBlock consecutive pixels.
+__device__ __forceinline__ void resolve_block(const CclImage& single, const CclMap& map,
+                                              CclImage* g, int* blk) {
+    if (map.images) {
+        const int img = map.blk_image[blockIdx.x];
+        *g = map.images[img];
+        *blk = static_cast<int>(blockIdx.x) - map.blk_first[img];
+    } else {
+        *g = single;
+        *blk = blockIdx.x;
+    }
+}
+
 __device__ __forceinline__ int lds_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -107,13 +138,18 @@ __device__ void lds_unite(int* P, int a, int b) {
 // equal labels from a ballot of run starts, and union-find then links run
 // heads only, once per vertical overlap of two runs.  Writes P[i] = global
 // index of i's local root, lroot[i] = its local index, and clears size[i].
-__global__ __launch_bounds__(kBlock) void ccl_local_kernel(const int32_t* __restrict__ labels,
-                                                           int w, int h, int* __restrict__ P,
-                                                           int* __restrict__ lroot,
-                                                           int* __restrict__ size) {
+__global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclMap map) {
     __shared__ int lab[kTilePx];
     __shared__ int par[kTilePx];
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    CclImage g;
+    int bx, by;
+    resolve_tile(single, map, &g, &bx, &by);
+    const int32_t* __restrict__ labels = g.labels;
+    int* __restrict__ P = g.comp;
+    int* __restrict__ lroot = g.lroot;
+    int* __restrict__ size = g.size;
+    const int w = g.w, h = g.h;
+    const int x0 = bx * kTile, y0 = by * kTile;
     const int col = threadIdx.x % kTile;
     int v[kPxPerThread];
 #pragma unroll
@@ -163,9 +199,14 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(const int32_t* __rest
 }
 
 // Unions across the left and top borders of every tile.
-__global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(const int32_t* __restrict__ labels,
-                                                               int w, int h, int* P) {
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+__global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, CclMap map) {
+    CclImage g;
+    int bx, by;
+    resolve_tile(single, map, &g, &bx, &by);
+    const int32_t* __restrict__ labels = g.labels;
+    int* P = g.comp;
+    const int w = g.w, h = g.h;
+    const int x0 = bx * kTile, y0 = by * kTile;
     const int t = threadIdx.x;
     if (t < kTile) {
         const int x = x0, y = y0 + t;
@@ -185,12 +226,17 @@ __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(const int32_t* __
 // walk the forest (the thread's walks advanced together, with unconditional
 // loads, so that they overlap); every pixel then takes its local root's
 // result from LDS.
-__global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int w, int h, int* P,
-                                                             const int* __restrict__ lroot,
-                                                             int* __restrict__ size) {
+__global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, CclMap map) {
     __shared__ int cnt[kTilePx];
     __shared__ int root[kTilePx];
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    CclImage g;
+    int bx, by;
+    resolve_tile(single, map, &g, &bx, &by);
+    int* P = g.comp;
+    const int* __restrict__ lroot = g.lroot;
+    int* __restrict__ size = g.size;
+    const int w = g.w, h = g.h;
+    const int x0 = bx * kTile, y0 = by * kTile;
     int lr[kPxPerThread], x[kPxPerThread];
     bool in[kPxPerThread];
 #pragma unroll
@@ -260,11 +306,17 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(int w, int h, int* 
 constexpr int kMergePx = 4;
 constexpr int kMergeBlock = kBlock * kMergePx;
 
-__global__ __launch_bounds__(kBlock) void ccl_merge_kernel(
-    int n, int w, long long S2, int min_segment, const int* __restrict__ comp,
-    const int* __restrict__ size, int* __restrict__ rank, int* __restrict__ block_count) {
+__global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclMap map) {
     __shared__ int part[kMergePx * (kBlock / 64)];
-    const int base = blockIdx.x * kMergeBlock + threadIdx.x;
+    CclImage g;
+    int blk;
+    resolve_block(single, map, &g, &blk);
+    const int n = g.w * g.h, w = g.w, min_segment = g.min_segment;
+    const long long S2 = g.S2;
+    const int* __restrict__ comp = g.comp;
+    const int* __restrict__ size = g.size;
+    int* __restrict__ rank = g.rank;
+    const int base = blk * kMergeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool root[kMergePx];
     int sz[kMergePx], tgt[kMergePx];
@@ -302,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(
     if (threadIdx.x == 0) {
         int total = 0;
         for (int q = 0; q < kMergePx * (kBlock / 64); ++q) total += part[q];
-        block_count[blockIdx.x] = total;
+        g.block_count[blk] = total;
     }
 }
 
@@ -345,15 +397,18 @@ constexpr int kFusedScanMax = 4096;
 // counts and every workgroup derives the offsets itself (workgroup 0 also
 // stores the total); otherwise it holds the offsets already.
 template <bool kScan>
-__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int nblocks,
-                                                             const int* __restrict__ comp,
-                                                             int* rank,
-                                                             const int* __restrict__ block_count,
-                                                             int32_t* __restrict__ out,
-                                                             int32_t* __restrict__ n_segments) {
+__global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, CclMap map) {
     extern __shared__ int s_off[];  // kScan: nblocks offsets
     __shared__ int wave_part[kBlock / 64];
-    const int base = blockIdx.x * kMergeBlock + threadIdx.x;
+    CclImage g;
+    int blk;
+    resolve_block(single, map, &g, &blk);
+    const int n = g.w * g.h, nblocks = g.nmerge;
+    const int* __restrict__ comp = g.comp;
+    int* rank = g.rank;
+    const int* __restrict__ block_count = g.block_count;
+    int32_t* __restrict__ out = g.out;
+    const int base = blk * kMergeBlock + threadIdx.x;
     int r[kMergePx], k[kMergePx];
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j)  // clamped: loads issued together
@@ -400,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int nblocks,
             run += c;
         }
         __syncthreads();
-        if (blockIdx.x == 0 && threadIdx.x == 0 && n_segments) *n_segments = total;
+        if (blk == 0 && threadIdx.x == 0 && g.n_segments) *g.n_segments = total;
     }
     // Follow the joins to a surviving root, one rank load per step, the
     // thread's walks advanced together (finished ones reload their root,
@@ -449,46 +504,76 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(int n, int nblocks,
 
 int scan_tiles_for(int n) { return (n + kMergeBlock - 1) / kMergeBlock; }
 
-hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
-                               int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
-                               hipStream_t s) {
-    const int n = w * h;
-    int* comp = ws.ccl0;  // local roots, then component roots, then join links
-    int* size = ws.ccl1;  // component sizes
-    int* rank = ws.ccl2;  // ranks of the surviving roots
-    int* lroot = ws.ccl3; // local roots (index inside the tile)
-    hipError_t e;
+CclImage ccl_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int32_t min_segment,
+                   int32_t* labels_out, int32_t* n_segments) {
+    CclImage c;
+    c.labels = ws.labels;
+    c.out = labels_out;
+    c.comp = ws.ccl0;   // local roots, then component roots
+    c.size = ws.ccl1;   // component sizes
+    c.rank = ws.ccl2;   // ranks of the surviving roots, join links of the others
+    c.lroot = ws.ccl3;  // local roots (index inside the tile)
+    c.block_count = ws.scan;  // per-block surviving roots (then their offsets)
+    c.n_segments = n_segments;
+    c.w = w;
+    c.h = h;
+    c.S2 = static_cast<long long>(g.S) * g.S;
+    c.min_segment = min_segment;
+    c.tiles_x = (w + kTile - 1) / kTile;
+    c.nmerge = scan_tiles_for(w * h);
+    return c;
+}
+
+int ccl_tiles_for(int32_t w, int32_t h) {
+    return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+}
+
+bool ccl_batch_supported(int32_t w, int32_t h) { return scan_tiles_for(w * h) <= kFusedScanMax; }
+
 #define SLIC_STEP(name, ...)                                 \
     do {                                                     \
         KernelTimer t_(name, s);                             \
         __VA_ARGS__;                                         \
         if ((e = hipGetLastError()) != hipSuccess) return e; \
     } while (0)
-    int* block_count = ws.scan;  // per-block surviving roots, then their offsets
+
+hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                               int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
+                               hipStream_t s) {
+    const CclImage c = ccl_image(ws, w, h, g, min_segment, labels_out, n_segments);
+    const CclMap none{};
+    hipError_t e;
     const dim3 tiles((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
-    SLIC_STEP("ccl_local",
-              ccl_local_kernel<<<tiles, kBlock, 0, s>>>(ws.labels, w, h, comp, lroot, size));
-    SLIC_STEP("ccl_border", ccl_border_kernel<<<tiles, 2 * kTile, 0, s>>>(ws.labels, w, h, comp));
-    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(w, h, comp, lroot, size));
-    const int nmerge = scan_tiles_for(n);
-    SLIC_STEP("ccl_merge",
-              ccl_merge_kernel<<<nmerge, kBlock, 0, s>>>(
-                  n, w, static_cast<long long>(g.S) * g.S, min_segment, comp, size, rank,
-                  block_count));
-    if (nmerge <= kFusedScanMax) {
-        SLIC_STEP("ccl_relabel",
-                  ccl_relabel_kernel<true><<<nmerge, kBlock, nmerge * sizeof(int), s>>>(
-                      n, nmerge, comp, rank, block_count, labels_out, n_segments));
+    SLIC_STEP("ccl_local", ccl_local_kernel<<<tiles, kBlock, 0, s>>>(c, none));
+    SLIC_STEP("ccl_border", ccl_border_kernel<<<tiles, 2 * kTile, 0, s>>>(c, none));
+    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(c, none));
+    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<c.nmerge, kBlock, 0, s>>>(c, none));
+    if (c.nmerge <= kFusedScanMax) {
+        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<c.nmerge, kBlock,
+                                                             c.nmerge * sizeof(int), s>>>(c, none));
     } else {
-        SLIC_STEP("ccl_scan",
-                  ccl_scan_kernel<<<1, kBlock, 0, s>>>(nmerge, block_count, n_segments));
-        SLIC_STEP("ccl_relabel",
-                  ccl_relabel_kernel<false><<<nmerge, kBlock, 0, s>>>(
-                      n, nmerge, comp, rank, block_count, labels_out, nullptr));
+        SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(c.nmerge, c.block_count,
+                                                                   c.n_segments));
+        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<false><<<c.nmerge, kBlock, 0, s>>>(c, none));
     }
-#undef SLIC_STEP
     return hipSuccess;
 }
+
+hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int total_blocks,
+                                     int max_nmerge, hipStream_t s) {
+    if (!map.images || max_nmerge > kFusedScanMax) return hipErrorInvalidValue;
+    const CclImage unused{};
+    hipError_t e;
+    SLIC_STEP("ccl_local", ccl_local_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_border", ccl_border_kernel<<<total_tiles, 2 * kTile, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<total_blocks, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<total_blocks, kBlock,
+                                                         max_nmerge * sizeof(int), s>>>(unused, map));
+    return hipSuccess;
+}
+
+#undef SLIC_STEP
 
 // Stray-pixel filter (Section 3's clean-up: two one-thread-per-pixel passes
 // of one kernel).  A pixel none of whose 4-neighbours inside the image shares

@@ -130,6 +130,43 @@ hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& 
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
                                hipStream_t s);
+
+// Connectivity of one image: device pointers into its workspace and sizes.
+struct CclImage {
+    const int32_t* labels;  // association labels (input)
+    int32_t* out;           // final labels (may be `labels`)
+    int32_t* comp;          // local roots, then component roots
+    int32_t* size;          // component sizes
+    int32_t* rank;          // survivor ranks and join links
+    int32_t* lroot;         // local roots (index inside the 32 x 32 tile)
+    int32_t* block_count;   // survivors per run of 1024 pixels
+    int32_t* n_segments;    // the segment count (may be null)
+    int w, h;
+    long long S2;           // S * S
+    int min_segment;
+    int tiles_x;            // 32 x 32 tiles per row
+    int nmerge;             // runs of 1024 pixels
+};
+
+// Batch connectivity: workgroup b of a tile pass works on tile
+// b - tile_first[i] of image i = tile_image[b]; of a pixel-run pass on run
+// b - blk_first[i] of image i = blk_image[b] (all in device memory).
+struct CclMap {
+    const CclImage* images;
+    const int* tile_image;
+    const int* tile_first;
+    const int* blk_image;
+    const int* blk_first;
+};
+
+CclImage ccl_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int32_t min_segment,
+                   int32_t* labels_out, int32_t* n_segments);
+int ccl_tiles_for(int32_t w, int32_t h);
+// Whether an image can take part in a batched connectivity launch (its
+// segment numbering fits the relabel pass's own scan).
+bool ccl_batch_supported(int32_t w, int32_t h);
+hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int total_blocks,
+                                     int max_nmerge, hipStream_t s);
 // Section 3's stray-pixel filter on `labels` in place (ws.ccl0 as the second
 // buffer), `passes` passes.
 hipError_t launch_stray_filter(const Workspace& ws, int32_t w, int32_t h, int32_t* labels,
