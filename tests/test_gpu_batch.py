@@ -137,3 +137,21 @@ def test_batch_rejects_bad_arguments(slic):
     with pytest.raises(_abi.SlicError):  # host memory
         _abi.slic_batch_create([p.c()], [host.data_ptr()], [lab.data_ptr()], 2, 0, None, 0, 0,
                                ws.data_ptr(), ws.numel())
+
+
+def test_batch_with_a_large_image_takes_the_per_image_connectivity(slic):
+    """A 4.35 Mpix image's segment numbering does not fit the batched relabel
+    pass's own scan (4096 runs of 1024 pixels), so the batch runs the
+    connectivity image by image; the results equal single calls either way."""
+    wls = [Workload("big", 2560, 1700, 400, 8.0, 4242, 32, iters=1),
+           Workload("small", 120, 90, 30, 8.0, 4243, 8, iters=1)]
+    imgs = [synth.image_for(w) for w in wls]
+    params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb) for w in wls]
+    b = slic.Batch(params, [_device(i) for i in imgs], 1, enforce=True, use_graph=False)
+    b.run()
+    torch.cuda.synchronize()
+    for wl, img, got, n in zip(wls, imgs, b.labels, b.n_segments.cpu().numpy()):
+        want = _single(slic, wl, img, 1, True)
+        assert np.array_equal(got.cpu().numpy(), want["labels"].cpu().numpy()), wl.name
+        assert n == int(want["n_segments"].cpu()[0])
+    b.close()
