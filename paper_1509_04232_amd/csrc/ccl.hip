@@ -68,22 +68,21 @@ constexpr int kTile = 32;
 constexpr int kTilePx = kTile * kTile;
 constexpr int kPxPerThread = kTilePx / kBlock;
 
-// A workgroup's image and its tile (x, y) among the image's 32 x 32 tiles:
-// from the kernel argument and the launch grid (one image) or, for a batch,
-// from the image table through the tile-to-image map.
-__device__ __forceinline__ void resolve_tile(const CclImage& single, const CclMap& map,
+// The image of tile number idx of a launch and the tile's (x, y) among the
+// image's 32 x 32 tiles: from the kernel argument (one image) or, for a
+// batch, from the image table through the tile-to-image map.
+__device__ __forceinline__ void resolve_tile(const CclImage& single, const CclMap& map, int idx,
                                              CclImage* g, int* bx, int* by) {
+    int local = idx;
     if (map.images) {
-        const int img = map.tile_image[blockIdx.x];
+        const int img = map.tile_image[idx];
         *g = map.images[img];
-        const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
-        *bx = local % g->tiles_x;
-        *by = local / g->tiles_x;
+        local -= map.tile_first[img];
     } else {
         *g = single;
-        *bx = blockIdx.x;
-        *by = blockIdx.y;
     }
+    *bx = local % g->tiles_x;
+    *by = local / g->tiles_x;
 }
 
 // Likewise for the passes over runs of kMergeBlock consecutive pixels.
@@ -143,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
     __shared__ int par[kTilePx];
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, &g, &bx, &by);
+    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
     const int32_t* __restrict__ labels = g.labels;
     int* __restrict__ P = g.comp;
     int* __restrict__ lroot = g.lroot;
@@ -202,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
 __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, CclMap map) {
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, &g, &bx, &by);
+    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
     const int32_t* __restrict__ labels = g.labels;
     int* P = g.comp;
     const int w = g.w, h = g.h;
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
     __shared__ int root[kTilePx];
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, &g, &bx, &by);
+    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
     int* P = g.comp;
     const int* __restrict__ lroot = g.lroot;
     int* __restrict__ size = g.size;
@@ -293,49 +292,93 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
 // both have smaller roots, so the joins form a forest whose tree roots are
 // the smallest indices of their trees and are exactly the components that
 // are not small (or hold pixel 0).  After the flatten pass every entry of
-// comp holds its pixel's component root and nothing writes comp any more, so
-// a small root records its join target directly as rank[r] = -2 - comp[q]
-// (q the pixel left of or above r); a surviving root gets its rank in raster
-// order among the workgroup's survivors (ballot prefix counts), and the
-// workgroup stores their count.
+// comp holds its pixel's component root and nothing writes comp any more.
 //
-// A workgroup covers kMergeBlock consecutive pixels; thread t handles pixels
-// t, t + kBlock, ... of them, so every load of the pass is coalesced.  Loads
-// are unconditional (positions past the image are clamped) so that a
+// The merge launch has two kinds of workgroups.  The first n_number number
+// the surviving roots: each covers kMergeBlock consecutive pixels (thread t
+// handles pixels t, t + kBlock, ...), gives its survivors their rank in
+// raster order among the workgroup's survivors (ballot prefix counts) and
+// stores their count.  The others each take a 32 x 32 tile and record the
+// join of every small root in it as rank[r] = -2 - target, where target is
+// the first root along the chain of joins that is not a small root of the
+// same tile: the joins inside a tile are followed in LDS, so the relabel
+// pass only walks the joins that cross tiles (on noisy label maps a chain of
+// small components, each joining its left neighbour, can be dozens long).
+// Loads are unconditional (positions past the image are clamped) so that a
 // thread's loads are issued together rather than one branch at a time.
 constexpr int kMergePx = 4;
 constexpr int kMergeBlock = kBlock * kMergePx;
 
-__global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclMap map) {
+__device__ __forceinline__ bool is_small(const CclImage& g, int sz) {
+    return g.min_segment > 0 ? sz < g.min_segment : 4ll * sz < g.S2;
+}
+
+__global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclMap map,
+                                                           int n_number) {
     __shared__ int part[kMergePx * (kBlock / 64)];
+    __shared__ int link[kTilePx];
     CclImage g;
+    if (static_cast<int>(blockIdx.x) >= n_number) {
+        // ---- joins of the small roots of one tile
+        int bx, by;
+        resolve_tile(single, map, blockIdx.x - n_number, &g, &bx, &by);
+        const int w = g.w, h = g.h;
+        const int x0 = bx * kTile, y0 = by * kTile;
+        int gi[kPxPerThread], t[kPxPerThread];
+        bool small[kPxPerThread];
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) {
+            const int li = threadIdx.x + j * kBlock;
+            const int px = x0 + li % kTile, py = y0 + li / kTile;
+            const bool in = px < w && py < h;
+            const int pxc = min(px, w - 1), pyc = min(py, h - 1);
+            gi[j] = pyc * w + pxc;
+            const int c = g.comp[gi[j]];
+            const int sz = g.size[gi[j]];
+            t[j] = g.comp[pxc > 0 ? gi[j] - 1 : max(gi[j] - w, 0)];  // left, or above
+            const bool root = in && c == gi[j];
+            small[j] = root && gi[j] != 0 && is_small(g, sz);
+            // link: a tile slot for a target inside the tile, -4 - target for
+            // one outside, -1 for a surviving root, -2 for a pixel that is
+            // not a root (never reached: targets are roots)
+            int l = root ? -1 : -2;
+            if (small[j]) {
+                const int ty = t[j] / w, tx = t[j] - ty * w;
+                const bool inside = tx >= x0 && tx < x0 + kTile && ty >= y0 && ty < y0 + kTile;
+                l = inside ? (ty - y0) * kTile + (tx - x0) : -4 - t[j];
+            }
+            link[li] = l;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) {
+            if (!small[j]) continue;
+            int l = link[threadIdx.x + j * kBlock], slot = -1;
+            while (l >= 0) {  // links point to smaller slots: the walk ends
+                slot = l;
+                l = link[slot];
+            }
+            const int target = l <= -4 ? -4 - l : (y0 + slot / kTile) * w + x0 + slot % kTile;
+            g.rank[gi[j]] = -2 - target;
+        }
+        return;
+    }
+    // ---- numbering of the surviving roots of kMergeBlock consecutive pixels
     int blk;
     resolve_block(single, map, &g, &blk);
-    const int n = g.w * g.h, w = g.w, min_segment = g.min_segment;
-    const long long S2 = g.S2;
+    const int n = g.w * g.h;
     const int* __restrict__ comp = g.comp;
     const int* __restrict__ size = g.size;
     int* __restrict__ rank = g.rank;
     const int base = blk * kMergeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool root[kMergePx];
-    int sz[kMergePx], tgt[kMergePx];
-#pragma unroll
-    for (int j = 0; j < kMergePx; ++j) {
-        const int r = base + j * kBlock;
-        const int rc = min(r, n - 1);
-        root[j] = r < n && comp[rc] == r;
-        sz[j] = size[rc];
-        const int q = rc % w > 0 ? rc - 1 : rc - w;  // left of r, or above it
-        tgt[j] = comp[max(q, 0)];
-    }
     bool survives[kMergePx];
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) {
         const int r = base + j * kBlock;
-        const bool small = min_segment > 0 ? sz[j] < min_segment : 4ll * sz[j] < S2;
-        survives[j] = root[j] && (r == 0 || !small);
-        if (root[j] && !survives[j]) rank[r] = -2 - tgt[j];
+        const int rc = min(r, n - 1);
+        const bool root = r < n && comp[rc] == r;
+        survives[j] = root && (r == 0 || !is_small(g, size[rc]));
     }
     unsigned long long ballot[kMergePx];
 #pragma unroll
@@ -543,11 +586,12 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
     const CclImage c = ccl_image(ws, w, h, g, min_segment, labels_out, n_segments);
     const CclMap none{};
     hipError_t e;
-    const dim3 tiles((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    const int tiles = ccl_tiles_for(w, h);
     SLIC_STEP("ccl_local", ccl_local_kernel<<<tiles, kBlock, 0, s>>>(c, none));
     SLIC_STEP("ccl_border", ccl_border_kernel<<<tiles, 2 * kTile, 0, s>>>(c, none));
     SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(c, none));
-    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<c.nmerge, kBlock, 0, s>>>(c, none));
+    SLIC_STEP("ccl_merge",
+              ccl_merge_kernel<<<c.nmerge + tiles, kBlock, 0, s>>>(c, none, c.nmerge));
     if (c.nmerge <= kFusedScanMax) {
         SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<c.nmerge, kBlock,
                                                              c.nmerge * sizeof(int), s>>>(c, none));
@@ -567,7 +611,8 @@ hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int tot
     SLIC_STEP("ccl_local", ccl_local_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
     SLIC_STEP("ccl_border", ccl_border_kernel<<<total_tiles, 2 * kTile, 0, s>>>(unused, map));
     SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
-    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<total_blocks, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<total_blocks + total_tiles, kBlock, 0, s>>>(
+                               unused, map, total_blocks));
     SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<total_blocks, kBlock,
                                                          max_nmerge * sizeof(int), s>>>(unused, map));
     return hipSuccess;
