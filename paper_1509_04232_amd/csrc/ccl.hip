@@ -85,10 +85,26 @@ __device__ __forceinline__ void resolve_tile(const CclImage& single, const CclMa
     *by = local / g->tiles_x;
 }
 
+// The tile passes: one image on a two-dimensional grid of tiles (kBatch
+// false: no table lookups and no division on the way in), or a batch on a
+// one-dimensional grid through the map.
+template <bool kBatch>
+__device__ __forceinline__ void tile_of_launch(const CclImage& single, const CclMap& map,
+                                               CclImage* g, int* bx, int* by) {
+    if constexpr (kBatch) {
+        resolve_tile(single, map, blockIdx.x, g, bx, by);
+    } else {
+        *g = single;
+        *bx = blockIdx.x;
+        *by = blockIdx.y;
+    }
+}
+
 // Likewise for the passes over runs of kMergeBlock consecutive pixels.
+template <bool kBatch>
 __device__ __forceinline__ void resolve_block(const CclImage& single, const CclMap& map,
                                               CclImage* g, int* blk) {
-    if (map.images) {
+    if constexpr (kBatch) {
         const int img = map.blk_image[blockIdx.x];
         *g = map.images[img];
         *blk = static_cast<int>(blockIdx.x) - map.blk_first[img];
@@ -137,12 +153,13 @@ __device__ void lds_unite(int* P, int a, int b) {
 // equal labels from a ballot of run starts, and union-find then links run
 // heads only, once per vertical overlap of two runs.  Writes P[i] = global
 // index of i's local root, lroot[i] = its local index, and clears size[i].
+template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclMap map) {
     __shared__ int lab[kTilePx];
     __shared__ int par[kTilePx];
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
+    tile_of_launch<kBatch>(single, map, &g, &bx, &by);
     const int32_t* __restrict__ labels = g.labels;
     int* __restrict__ P = g.comp;
     int* __restrict__ lroot = g.lroot;
@@ -198,10 +215,11 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
 }
 
 // Unions across the left and top borders of every tile.
+template <bool kBatch>
 __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, CclMap map) {
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
+    tile_of_launch<kBatch>(single, map, &g, &bx, &by);
     const int32_t* __restrict__ labels = g.labels;
     int* P = g.comp;
     const int w = g.w, h = g.h;
@@ -225,12 +243,13 @@ __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, 
 // walk the forest (the thread's walks advanced together, with unconditional
 // loads, so that they overlap); every pixel then takes its local root's
 // result from LDS.
+template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, CclMap map) {
     __shared__ int cnt[kTilePx];
     __shared__ int root[kTilePx];
     CclImage g;
     int bx, by;
-    resolve_tile(single, map, blockIdx.x, &g, &bx, &by);
+    tile_of_launch<kBatch>(single, map, &g, &bx, &by);
     int* P = g.comp;
     const int* __restrict__ lroot = g.lroot;
     int* __restrict__ size = g.size;
@@ -313,6 +332,7 @@ __device__ __forceinline__ bool is_small(const CclImage& g, int sz) {
     return g.min_segment > 0 ? sz < g.min_segment : 4ll * sz < g.S2;
 }
 
+template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclMap map,
                                                            int n_number) {
     __shared__ int part[kMergePx * (kBlock / 64)];
@@ -321,7 +341,14 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
     if (static_cast<int>(blockIdx.x) >= n_number) {
         // ---- joins of the small roots of one tile
         int bx, by;
-        resolve_tile(single, map, blockIdx.x - n_number, &g, &bx, &by);
+        const int idx = static_cast<int>(blockIdx.x) - n_number;
+        if constexpr (kBatch) {
+            resolve_tile(single, map, idx, &g, &bx, &by);
+        } else {
+            g = single;
+            bx = idx % g.tiles_x;
+            by = idx / g.tiles_x;
+        }
         const int w = g.w, h = g.h;
         const int x0 = bx * kTile, y0 = by * kTile;
         int gi[kPxPerThread], t[kPxPerThread];
@@ -365,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
     }
     // ---- numbering of the surviving roots of kMergeBlock consecutive pixels
     int blk;
-    resolve_block(single, map, &g, &blk);
+    resolve_block<kBatch>(single, map, &g, &blk);
     const int n = g.w * g.h;
     const int* __restrict__ comp = g.comp;
     const int* __restrict__ size = g.size;
@@ -439,13 +466,13 @@ constexpr int kFusedScanMax = 4096;
 // map as the merge pass.  With kScan, block_count holds the merge pass's
 // counts and every workgroup derives the offsets itself (workgroup 0 also
 // stores the total); otherwise it holds the offsets already.
-template <bool kScan>
+template <bool kScan, bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, CclMap map) {
     extern __shared__ int s_off[];  // kScan: nblocks offsets
     __shared__ int wave_part[kBlock / 64];
     CclImage g;
     int blk;
-    resolve_block(single, map, &g, &blk);
+    resolve_block<kBatch>(single, map, &g, &blk);
     const int n = g.w * g.h, nblocks = g.nmerge;
     const int* __restrict__ comp = g.comp;
     int* rank = g.rank;
@@ -587,18 +614,19 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
     const CclMap none{};
     hipError_t e;
     const int tiles = ccl_tiles_for(w, h);
-    SLIC_STEP("ccl_local", ccl_local_kernel<<<tiles, kBlock, 0, s>>>(c, none));
-    SLIC_STEP("ccl_border", ccl_border_kernel<<<tiles, 2 * kTile, 0, s>>>(c, none));
-    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<tiles, kBlock, 0, s>>>(c, none));
+    const dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    SLIC_STEP("ccl_local", ccl_local_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
+    SLIC_STEP("ccl_border", ccl_border_kernel<false><<<grid, 2 * kTile, 0, s>>>(c, none));
+    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
     SLIC_STEP("ccl_merge",
-              ccl_merge_kernel<<<c.nmerge + tiles, kBlock, 0, s>>>(c, none, c.nmerge));
+              ccl_merge_kernel<false><<<c.nmerge + tiles, kBlock, 0, s>>>(c, none, c.nmerge));
     if (c.nmerge <= kFusedScanMax) {
-        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<c.nmerge, kBlock,
+        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true, false><<<c.nmerge, kBlock,
                                                              c.nmerge * sizeof(int), s>>>(c, none));
     } else {
         SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(c.nmerge, c.block_count,
                                                                    c.n_segments));
-        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<false><<<c.nmerge, kBlock, 0, s>>>(c, none));
+        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<false, false><<<c.nmerge, kBlock, 0, s>>>(c, none));
     }
     return hipSuccess;
 }
@@ -608,12 +636,14 @@ hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int tot
     if (!map.images || max_nmerge > kFusedScanMax) return hipErrorInvalidValue;
     const CclImage unused{};
     hipError_t e;
-    SLIC_STEP("ccl_local", ccl_local_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
-    SLIC_STEP("ccl_border", ccl_border_kernel<<<total_tiles, 2 * kTile, 0, s>>>(unused, map));
-    SLIC_STEP("ccl_flatten", ccl_flatten_kernel<<<total_tiles, kBlock, 0, s>>>(unused, map));
-    SLIC_STEP("ccl_merge", ccl_merge_kernel<<<total_blocks + total_tiles, kBlock, 0, s>>>(
+    SLIC_STEP("ccl_local", ccl_local_kernel<true><<<total_tiles, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_border",
+              ccl_border_kernel<true><<<total_tiles, 2 * kTile, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_flatten",
+              ccl_flatten_kernel<true><<<total_tiles, kBlock, 0, s>>>(unused, map));
+    SLIC_STEP("ccl_merge", ccl_merge_kernel<true><<<total_blocks + total_tiles, kBlock, 0, s>>>(
                                unused, map, total_blocks));
-    SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true><<<total_blocks, kBlock,
+    SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true, true><<<total_blocks, kBlock,
                                                          max_nmerge * sizeof(int), s>>>(unused, map));
     return hipSuccess;
 }
