@@ -125,9 +125,10 @@ __device__ __forceinline__ void store_i4(gmem<int32_t>* p, int a, int b, int c, 
 
 // A workgroup's image: from the kernel argument (one image) or, for a batch,
 // from the image table through the tile-to-image map.
+template <bool kBatch>
 __device__ __forceinline__ void resolve_image(const AssignImage& single, const AssignTileMap& map,
                                               AssignImage* g, int* bx, int* by) {
-    if (map.images) {
+    if constexpr (kBatch) {
         const int img = map.tile_image[blockIdx.x];
         *g = map.images[img];
         const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
@@ -187,15 +188,21 @@ __device__ __forceinline__ float dist_squared(float cl, float ca, float cb, floa
     return s + sp;
 }
 
+// Launch modes: one image, one image with the convergence stop, a batch.
+// Each is its own instantiation, so a kernel reads only the arguments its
+// mode uses and takes no branch on them on the way in.
+enum AssignMode { kModeSingle = 0, kModeConverge = 1, kModeBatch = 2 };
+
 // The Eq. 1 variants are held to 128 VGPRs (four waves per SIMD), which
 // they need for latency hiding at large frames.
-template <int VEC, int ROWS, int DIST>
+template <int VEC, int ROWS, int DIST, int MODE>
 __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     AssignImage single, AssignTileMap map, long long t, Converge cv) {
     using Sh = Shape<VEC, ROWS>;
+    constexpr bool kConv = MODE == kModeConverge;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_shift;
-    if (cv.ctl) {  // convergence stop: every workgroup takes the same decision
+    if constexpr (kConv) {  // convergence stop: every workgroup takes the same decision
         if (cv.ctl[3] != 0) return;
         if (t > cv.t_first && cv.ctl[(t - 1) % 3] < cv.limit) {
             if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     long long my_shift = 0;
     AssignImage g;
     int bx, by;
-    resolve_image(single, map, &g, &bx, &by);
+    resolve_image<MODE == kModeBatch>(single, map, &g, &bx, &by);
     const size_t ring = static_cast<size_t>(g.K) * kSumStride;
     gmem<long long>* const sums = as_global(g.sums);
     gmem<long long>* const sums_acc = sums + ring * static_cast<size_t>(t % 3);
@@ -321,7 +328,7 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
                             moved ? m4.w : old4.w);
             vy = moved ? my : oldy;
             if (owner && moved) {
-                if (cv.ctl) {  // L1 shift, each component rint(|d| 2^18)
+                if constexpr (kConv) {  // L1 shift, each component rint(|d| 2^18)
                     const double q = static_cast<double>(1 << kQShift);
                     my_shift += llrint(fabs(static_cast<double>(v.x) - old4.x) * q) +
                                 llrint(fabs(static_cast<double>(v.y) - old4.y) * q) +
@@ -456,8 +463,10 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     }
     if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
     __syncthreads();
-    if (cv.ctl && threadIdx.x == 0 && s_shift)
-        atomicAdd(reinterpret_cast<unsigned long long*>(cv.ctl + t % 3), s_shift);
+    if constexpr (kConv) {
+        if (threadIdx.x == 0 && s_shift)
+            atomicAdd(reinterpret_cast<unsigned long long*>(cv.ctl + t % 3), s_shift);
+    }
 
     // ---- add the workgroup's bins to the global sums
     for (int i = threadIdx.x; i < ncells; i += kThreads) {
@@ -567,8 +576,14 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
         grid = dim3((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
     }
     KernelTimer timer("assign", s);
-    assign_kernel<VEC, ROWS, DIST><<<grid, kThreads, variant_lds<VEC, ROWS>(min_S), s>>>(a, map, t,
-                                                                                       cv);
+    const size_t lds = variant_lds<VEC, ROWS>(min_S);
+    if (map.images) {
+        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+    } else if (cv.ctl) {
+        assign_kernel<VEC, ROWS, DIST, kModeConverge><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+    } else {
+        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+    }
     return hipGetLastError();
 }
 
