@@ -156,6 +156,10 @@ constexpr int kSW = kTW + 2 * kHalo, kSH = kTH + 2 * kHalo;  // staged tile
 constexpr int kThreads = 1024;
 constexpr int kSeedsPerPass = kThreads / 9;
 
+// kBatch: the workgroup's image comes from the tile map (a batch) rather
+// than the kernel argument; separate instantiations, so a single-image
+// launch reads no table and takes no branch on the way in.
+template <bool kBatch>
 __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single, LabSeedTileMap map,
                                                             LabTables tab) {
     __shared__ float lin[256];
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single,
     if (threadIdx.x < 256) lin[threadIdx.x] = tab.lin[threadIdx.x];
     LabSeedImage g;
     int bx, by;
-    if (map.images) {  // batch: this workgroup's image from the tile map
+    if constexpr (kBatch) {  // batch: this workgroup's image from the tile map
         const int img = map.tile_image[blockIdx.x];
         g = map.images[img];
         const int local = static_cast<int>(blockIdx.x) - map.tile_first[img];
@@ -311,7 +315,7 @@ hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pit
     const LabSeedTileMap none{nullptr, nullptr, nullptr};
     dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
     KernelTimer t("lab_seed", s);
-    lab_seed_kernel<<<g, kThreads, 0, s>>>(a, none, tables());
+    lab_seed_kernel<false><<<g, kThreads, 0, s>>>(a, none, tables());
     return hipGetLastError();
 }
 
@@ -319,7 +323,7 @@ hipError_t launch_lab_seed_batch(const LabSeedTileMap& map, int total_tiles, hip
     if (!map.images) return hipErrorInvalidValue;
     LabSeedImage unused{};
     KernelTimer t("lab_seed", s);
-    lab_seed_kernel<<<total_tiles, kThreads, 0, s>>>(unused, map, tables());
+    lab_seed_kernel<true><<<total_tiles, kThreads, 0, s>>>(unused, map, tables());
     return hipGetLastError();
 }
 
