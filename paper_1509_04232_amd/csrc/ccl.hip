@@ -24,13 +24,29 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int load_relaxed(const int* p) {
+// Global (device) memory as a named address space.  Descriptors read from
+// a batch table hold generic pointers; accesses through them would compile
+// to flat instructions, which also count against the LDS wait counter, so
+// every kernel takes its arrays as global-address-space pointers.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <class T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+    return (gmem<T>*)p;
+}
+
+__device__ __forceinline__ int load_relaxed(gmem<int>* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int atomic_min(gmem<int>* p, int v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The roots of a and b, the two walks advanced together so that their
 // loads overlap.
-__device__ __forceinline__ void find_roots(int* P, int& a, int& b) {
+__device__ __forceinline__ void find_roots(gmem<int>* P, int& a, int& b) {
     int pa = load_relaxed(P + a), pb = load_relaxed(P + b);
     while (pa != a || pb != b) {
         a = pa;
@@ -43,16 +59,16 @@ __device__ __forceinline__ void find_roots(int* P, int& a, int& b) {
 // Merge the trees of a and b, linking the larger root under the smaller.
 // If another thread re-linked the root meanwhile, atomicMin returns that new
 // parent and the merge continues from it.
-__device__ void unite(int* P, int a, int b) {
+__device__ void unite(gmem<int>* P, int a, int b) {
     bool done;
     do {
         find_roots(P, a, b);
         if (a < b) {
-            const int old = atomicMin(P + b, a);
+            const int old = atomic_min(P + b, a);
             done = old == b;
             b = old;
         } else if (b < a) {
-            const int old = atomicMin(P + a, b);
+            const int old = atomic_min(P + a, b);
             done = old == a;
             a = old;
         } else {
@@ -160,10 +176,10 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
     CclImage g;
     int bx, by;
     tile_of_launch<kBatch>(single, map, &g, &bx, &by);
-    const int32_t* __restrict__ labels = g.labels;
-    int* __restrict__ P = g.comp;
-    int* __restrict__ lroot = g.lroot;
-    int* __restrict__ size = g.size;
+    gmem<const int32_t>* __restrict__ labels = as_global(g.labels);
+    gmem<int>* __restrict__ P = as_global(g.comp);
+    gmem<int>* __restrict__ lroot = as_global(g.lroot);
+    gmem<int>* __restrict__ size = as_global(g.size);
     const int w = g.w, h = g.h;
     const int x0 = bx * kTile, y0 = by * kTile;
     const int col = threadIdx.x % kTile;
@@ -220,8 +236,8 @@ __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, 
     CclImage g;
     int bx, by;
     tile_of_launch<kBatch>(single, map, &g, &bx, &by);
-    const int32_t* __restrict__ labels = g.labels;
-    int* P = g.comp;
+    gmem<const int32_t>* __restrict__ labels = as_global(g.labels);
+    gmem<int>* P = as_global(g.comp);
     const int w = g.w, h = g.h;
     const int x0 = bx * kTile, y0 = by * kTile;
     const int t = threadIdx.x;
@@ -250,9 +266,9 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
     CclImage g;
     int bx, by;
     tile_of_launch<kBatch>(single, map, &g, &bx, &by);
-    int* P = g.comp;
-    const int* __restrict__ lroot = g.lroot;
-    int* __restrict__ size = g.size;
+    gmem<int>* P = as_global(g.comp);
+    gmem<const int>* __restrict__ lroot = as_global(g.lroot);
+    gmem<int>* __restrict__ size = as_global(g.size);
     const int w = g.w, h = g.h;
     const int x0 = bx * kTile, y0 = by * kTile;
     int lr[kPxPerThread], x[kPxPerThread];
@@ -302,7 +318,8 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
         const int c = cnt[li];
-        if (c > 0) atomicAdd(size + root[li], c);
+        if (c > 0)
+            __hip_atomic_fetch_add(size + root[li], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -351,6 +368,9 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
         }
         const int w = g.w, h = g.h;
         const int x0 = bx * kTile, y0 = by * kTile;
+        gmem<const int>* __restrict__ comp = as_global(g.comp);
+        gmem<const int>* __restrict__ size = as_global(g.size);
+        gmem<int>* __restrict__ rank = as_global(g.rank);
         int gi[kPxPerThread], t[kPxPerThread];
         bool small[kPxPerThread];
 #pragma unroll
@@ -360,9 +380,9 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
             const bool in = px < w && py < h;
             const int pxc = min(px, w - 1), pyc = min(py, h - 1);
             gi[j] = pyc * w + pxc;
-            const int c = g.comp[gi[j]];
-            const int sz = g.size[gi[j]];
-            t[j] = g.comp[pxc > 0 ? gi[j] - 1 : max(gi[j] - w, 0)];  // left, or above
+            const int c = comp[gi[j]];
+            const int sz = size[gi[j]];
+            t[j] = comp[pxc > 0 ? gi[j] - 1 : max(gi[j] - w, 0)];  // left, or above
             const bool root = in && c == gi[j];
             small[j] = root && gi[j] != 0 && is_small(g, sz);
             // link: a tile slot for a target inside the tile, -4 - target for
@@ -386,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
                 l = link[slot];
             }
             const int target = l <= -4 ? -4 - l : (y0 + slot / kTile) * w + x0 + slot % kTile;
-            g.rank[gi[j]] = -2 - target;
+            rank[gi[j]] = -2 - target;
         }
         return;
     }
@@ -394,9 +414,9 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
     int blk;
     resolve_block<kBatch>(single, map, &g, &blk);
     const int n = g.w * g.h;
-    const int* __restrict__ comp = g.comp;
-    const int* __restrict__ size = g.size;
-    int* __restrict__ rank = g.rank;
+    gmem<const int>* __restrict__ comp = as_global(g.comp);
+    gmem<const int>* __restrict__ size = as_global(g.size);
+    gmem<int>* __restrict__ rank = as_global(g.rank);
     const int base = blk * kMergeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool survives[kMergePx];
@@ -424,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
     if (threadIdx.x == 0) {
         int total = 0;
         for (int q = 0; q < kMergePx * (kBlock / 64); ++q) total += part[q];
-        g.block_count[blk] = total;
+        as_global(g.block_count)[blk] = total;
     }
 }
 
@@ -474,10 +494,10 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, Cc
     int blk;
     resolve_block<kBatch>(single, map, &g, &blk);
     const int n = g.w * g.h, nblocks = g.nmerge;
-    const int* __restrict__ comp = g.comp;
-    int* rank = g.rank;
-    const int* __restrict__ block_count = g.block_count;
-    int32_t* __restrict__ out = g.out;
+    gmem<const int>* __restrict__ comp = as_global(g.comp);
+    gmem<int>* rank = as_global(g.rank);
+    gmem<const int>* __restrict__ block_count = as_global(g.block_count);
+    gmem<int32_t>* __restrict__ out = as_global(g.out);
     const int base = blk * kMergeBlock + threadIdx.x;
     int r[kMergePx], k[kMergePx];
 #pragma unroll
@@ -525,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, Cc
             run += c;
         }
         __syncthreads();
-        if (blk == 0 && threadIdx.x == 0 && g.n_segments) *g.n_segments = total;
+        if (blk == 0 && threadIdx.x == 0 && g.n_segments) *as_global(g.n_segments) = total;
     }
     // Follow the joins to a surviving root, one rank load per step, the
     // thread's walks advanced together (finished ones reload their root,
