@@ -229,20 +229,17 @@ def bench_c2_batched(slic, torch, dev, n_frames: int, reps: int):
             "frames_per_s": round(n_frames / t, 1)}
 
 
-def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps: int,
-             hd: bool = False):
+def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps: int):
     """Workload c5: the learned warm start.  Trains the net on the GPU (crops
     of c5 training images, targets from plain 10-iteration SLIC), then on
-    ``n_eval`` evaluation images compares plain SLIC (convert + seed + 10
-    iterations) with the warm start (convert + net + 2 iterations + energy):
-    frames/s of each, the per-image energy ratio, the gate's pass rate
-    (E_warm <= 1.01 E_plain), frames/s with failing images charged warm +
-    plain time, and label agreement with plain SLIC."""
-    import numpy as np
-
+    ``n_eval`` evaluation images, at 640x480 and at 1920x1080, compares plain
+    SLIC (convert + seed + 10 iterations) with the warm start (convert + net
+    + 2 iterations + energy): frames/s of each, the per-image energy ratio,
+    the gate's pass rate (E_warm <= 1.01 E_plain), frames/s with failing
+    images charged warm + plain time, and label agreement with plain SLIC."""
     import synth
-    from synth.configs import warm_eval_workload, warm_train_workload
-    S, warm_iters, plain_iters = 16, 2, 10
+    from synth.configs import warm_train_workload
+    S, plain_iters = 16, 10
     t0 = time.perf_counter()
     train = []
     for j in range(n_train):
@@ -258,6 +255,24 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
+    result = {"images": n_eval, "S": S,
+              "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
+                        "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                        "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
+                        "loss": [[s, round(v, 4)] for s, v in log]}}
+    result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False))
+    result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True)
+    return result
+
+
+def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool):
+    """The trained net against plain SLIC on ``n_eval`` evaluation images of
+    640x480 (or 1920x1080 with ``hd``), one image at a time."""
+    import numpy as np
+
+    import synth
+    from synth.configs import warm_eval_workload
+    S, warm_iters, plain_iters = net.S, 2, 10
     evals = [warm_eval_workload(j, hd) for j in range(n_eval)]
     imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in evals]
     params = [slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb) for w in evals]
@@ -315,11 +330,7 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     e2 = e2.cpu().numpy()
     t_charged = t_warm + t_plain * float((~passed).sum()) / n_eval
     w0 = evals[0]
-    return {"images": n_eval, "size": f"{w0.width}x{w0.height}", "S": S,
-            "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
-                      "data_s": round(t_data, 2), "train_s": round(t_train, 2),
-                      "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
-                      "loss": [[s, round(v, 4)] for s, v in log]},
+    return {"size": f"{w0.width}x{w0.height}",
             "plain_iters": plain_iters, "warm_iters": warm_iters,
             "plain_frames_per_s": round(n_eval / t_plain, 1),
             "warm_frames_per_s": round(n_eval / t_warm, 1),
