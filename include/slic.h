@@ -194,7 +194,8 @@ int slic_autotune(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, i
 /* Batches: many images of uneven sizes and grid steps segmented together.
  * Every launch of the pipeline covers all images: one conversion+seeding
  * launch, 1 + n_iters association launches (workgroups walk a table of
- * (image, tile) pairs), then, with `enforce`, connectivity per image.  The
+ * (image, tile) pairs), then, with `enforce`, the five connectivity
+ * launches (per image instead when an image exceeds 4,194,304 pixels).  The
  * results equal n_images separate slic_segment calls bit for bit.
  *  - slic_batch_workspace_bytes: device workspace for the batch (every
  *    image's own workspace plus the tile tables); 0 if any params invalid.

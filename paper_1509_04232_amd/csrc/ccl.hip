@@ -474,13 +474,13 @@ __global__ __launch_bounds__(kBlock) void ccl_scan_kernel(int nblocks, int* __re
     if (threadIdx.x == kBlock - 1 && n_segments) *n_segments = part[kBlock - 1];
 }
 
-// Up to this many merge workgroups every relabel workgroup scans the
-// per-workgroup survivor counts itself, in LDS, and the one-workgroup scan
-// launch is skipped; beyond it the scan kernel runs first.
+// Up to this many runs of kMergeBlock pixels every relabel workgroup scans
+// the runs' survivor counts itself, in LDS, and the one-workgroup scan launch
+// is skipped; beyond it the scan kernel runs first.
 constexpr int kFusedScanMax = 4096;
 
 // Final labels: rank of the pixel's surviving root plus the number of
-// survivors in earlier merge workgroups.  comp[i] is the pixel's component
+// survivors in earlier runs.  comp[i] is the pixel's component
 // root; a surviving root carries its rank, a joined one -2 - (the root it
 // joins), and the joins are followed to the tree root.  Same pixel-to-thread
 // map as the merge pass.  With kScan, block_count holds the merge pass's
