@@ -587,10 +587,10 @@ def main() -> int:
     extra = {"kernels_c2_event_bracketed": {k: {"avg_us": round(v["avg_ms"] * 1e3, 3),
                                 "per_frame": v["launches_per_frame"]} for k, v in ktimes.items()}}
     if not args.no_extra:
-        for name in ("c2", "c3"):
+        for name in ("c1", "c2", "c3"):
             w = synth.WORKLOADS[name]
             f = frame if name == "c2" else Frame(slic, w, dev)
-            steps = max(20, args.steps // (1 if name == "c2" else 5))
+            steps = max(20, args.steps // (5 if name == "c3" else 1))
             t10 = time_frames(torch, f, steps, 5, 10, False)
             t0 = time_frames(torch, f, steps, 5, 0, False)
             t_iter = (t10 - t0) / 10
