@@ -155,3 +155,21 @@ def test_batch_with_a_large_image_takes_the_per_image_connectivity(slic):
         assert np.array_equal(got.cpu().numpy(), want["labels"].cpu().numpy()), wl.name
         assert n == int(want["n_segments"].cpu()[0])
     b.close()
+
+
+def test_batch_connectivity_with_per_image_thresholds(slic):
+    """Each image's own merge threshold reaches the batched connectivity
+    launches (min_segment from 0, the S*S/4 default, to large values)."""
+    wls = _mixed_workloads()[:6]
+    imgs = [synth.image_for(w) for w in wls]
+    thresholds = [0, 1, 5, 30, 200, 10_000]
+    params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb, min_segment=ms)
+              for w, ms in zip(wls, thresholds)]
+    b = slic.Batch(params, [_device(i) for i in imgs], 3, enforce=True, use_graph=True)
+    b.run()
+    torch.cuda.synchronize()
+    for wl, img, ms, got, n in zip(wls, imgs, thresholds, b.labels, b.n_segments.cpu().numpy()):
+        want = oracle.segment(img, wl.S, wl.m, 3, wl.perturb, True, ms)
+        assert np.array_equal(got.cpu().numpy(), want["seg_labels"]), (wl.name, ms)
+        assert n == want["n_segments"]
+    b.close()

@@ -137,6 +137,19 @@ def test_connectivity_numbering_both_scan_paths(slic, w, h):
     assert_parity(got, want, enforce=True)
 
 
+@pytest.mark.parametrize("w,h,S,ms", [(640, 480, 16, 0), (640, 480, 16, 6), (333, 257, 8, 2)])
+def test_connectivity_on_pure_noise(slic, w, h, S, ms):
+    """Uniform random pixels: the label map breaks into tens of thousands of
+    small components whose chains of joins run across many 32 x 32 tiles,
+    the deepest case for the merge and relabel passes.  With the default
+    threshold every component is small and all join pixel 0's (one segment);
+    small explicit thresholds leave thousands of segments."""
+    img = np.random.default_rng(w * h).integers(0, 256, (h, w, 3), dtype=np.uint8)
+    got = gpu_run(slic, img, S, 10.0, 2, True, enforce=True, min_segment=ms)
+    want = oracle_run(img, S, 10.0, 2, True, enforce=True, min_segment=ms)
+    assert_parity(got, want, enforce=True)
+
+
 @pytest.mark.parametrize("w,h,S", [(64, 48, 16), (40, 24, 8), (96, 96, 3)])
 def test_uniform_image_closed_form(slic, w, h, S):
     img = np.full((h, w, 3), (90, 140, 200), np.uint8)
