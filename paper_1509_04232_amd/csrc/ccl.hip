@@ -478,17 +478,19 @@ __global__ __launch_bounds__(kBlock) void ccl_scan_kernel(int nblocks, int* __re
 // the runs' survivor counts itself, in LDS, and the one-workgroup scan launch
 // is skipped; beyond it the scan kernel runs first.
 constexpr int kFusedScanMax = 4096;
+constexpr int kFusedScanSmall = 1024;  // a variant with fewer count loads per thread
 
 // Final labels: rank of the pixel's surviving root plus the number of
 // survivors in earlier runs.  comp[i] is the pixel's component
 // root; a surviving root carries its rank, a joined one -2 - (the root it
 // joins), and the joins are followed to the tree root.  Same pixel-to-thread
-// map as the merge pass.  With kScan, block_count holds the merge pass's
-// counts and every workgroup derives the offsets itself (workgroup 0 also
-// stores the total); otherwise it holds the offsets already.
-template <bool kScan, bool kBatch>
+// map as the merge pass.  With SQ > 0 (up to SQ * kBlock runs), block_count
+// holds the merge pass's counts and every workgroup derives the offsets
+// itself (workgroup 0 also stores the total); with SQ = 0 it holds the
+// offsets already.
+template <int SQ, bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, CclMap map) {
-    extern __shared__ int s_off[];  // kScan: nblocks offsets
+    extern __shared__ int s_off[];  // SQ > 0: nblocks offsets
     __shared__ int wave_part[kBlock / 64];
     CclImage g;
     int blk;
@@ -505,12 +507,12 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, Cc
         r[j] = comp[min(base + j * kBlock, n - 1)];
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) k[j] = rank[r[j]];
-    if constexpr (kScan) {
+    if constexpr (SQ > 0) {
         // exclusive prefix sums of the counts into s_off: coalesced loads
         // into LDS, each thread sums a run of consecutive counts, the runs'
         // sums are scanned with shuffles in each wavefront and then across
         // the wavefronts, and each thread writes its run's offsets back
-        constexpr int kQ = kFusedScanMax / kBlock;
+        constexpr int kQ = SQ;
         int cnt[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q)  // clamped, so every load is issued at once
@@ -577,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void ccl_relabel_kernel(CclImage single, Cc
         }
     }
     auto offset_of = [&](int root) {
-        if constexpr (kScan) {
+        if constexpr (SQ > 0) {
             return s_off[root / kMergeBlock];
         } else {
             return block_count[root / kMergeBlock];
@@ -640,13 +642,19 @@ hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const 
     SLIC_STEP("ccl_flatten", ccl_flatten_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
     SLIC_STEP("ccl_merge",
               ccl_merge_kernel<false><<<c.nmerge + tiles, kBlock, 0, s>>>(c, none, c.nmerge));
-    if (c.nmerge <= kFusedScanMax) {
-        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true, false><<<c.nmerge, kBlock,
-                                                             c.nmerge * sizeof(int), s>>>(c, none));
+    const size_t lds = c.nmerge * sizeof(int);
+    if (c.nmerge <= kFusedScanSmall) {
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<kFusedScanSmall / kBlock, false><<<c.nmerge, kBlock, lds, s>>>(
+                      c, none));
+    } else if (c.nmerge <= kFusedScanMax) {
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<kFusedScanMax / kBlock, false><<<c.nmerge, kBlock, lds, s>>>(
+                      c, none));
     } else {
         SLIC_STEP("ccl_scan", ccl_scan_kernel<<<1, kBlock, 0, s>>>(c.nmerge, c.block_count,
                                                                    c.n_segments));
-        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<false, false><<<c.nmerge, kBlock, 0, s>>>(c, none));
+        SLIC_STEP("ccl_relabel", ccl_relabel_kernel<0, false><<<c.nmerge, kBlock, 0, s>>>(c, none));
     }
     return hipSuccess;
 }
@@ -663,8 +671,16 @@ hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int tot
               ccl_flatten_kernel<true><<<total_tiles, kBlock, 0, s>>>(unused, map));
     SLIC_STEP("ccl_merge", ccl_merge_kernel<true><<<total_blocks + total_tiles, kBlock, 0, s>>>(
                                unused, map, total_blocks));
-    SLIC_STEP("ccl_relabel", ccl_relabel_kernel<true, true><<<total_blocks, kBlock,
-                                                         max_nmerge * sizeof(int), s>>>(unused, map));
+    const size_t lds = max_nmerge * sizeof(int);
+    if (max_nmerge <= kFusedScanSmall) {
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<kFusedScanSmall / kBlock, true><<<total_blocks, kBlock, lds, s>>>(
+                      unused, map));
+    } else {
+        SLIC_STEP("ccl_relabel",
+                  ccl_relabel_kernel<kFusedScanMax / kBlock, true><<<total_blocks, kBlock, lds, s>>>(
+                      unused, map));
+    }
     return hipSuccess;
 }
 
