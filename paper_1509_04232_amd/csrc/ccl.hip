@@ -371,24 +371,34 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
         gmem<const int>* __restrict__ comp = as_global(g.comp);
         gmem<const int>* __restrict__ size = as_global(g.size);
         gmem<int>* __restrict__ rank = as_global(g.rank);
-        int gi[kPxPerThread], t[kPxPerThread];
-        bool small[kPxPerThread];
+        int gi[kPxPerThread], t[kPxPerThread], sz[kPxPerThread];
+        bool small[kPxPerThread], root[kPxPerThread];
+        // the roots first (all loads issued together), then the size and the
+        // join target, which other pixels (most are not roots) read from
+        // pixel 0 instead: the loads stay unconditional, so they are issued
+        // together, and non-roots fetch one shared line
 #pragma unroll
         for (int j = 0; j < kPxPerThread; ++j) {
             const int li = threadIdx.x + j * kBlock;
             const int px = x0 + li % kTile, py = y0 + li / kTile;
-            const bool in = px < w && py < h;
-            const int pxc = min(px, w - 1), pyc = min(py, h - 1);
-            gi[j] = pyc * w + pxc;
+            gi[j] = min(py, h - 1) * w + min(px, w - 1);
             const int c = comp[gi[j]];
-            const int sz = size[gi[j]];
-            t[j] = comp[pxc > 0 ? gi[j] - 1 : max(gi[j] - w, 0)];  // left, or above
-            const bool root = in && c == gi[j];
-            small[j] = root && gi[j] != 0 && is_small(g, sz);
+            root[j] = px < w && py < h && c == gi[j];
+        }
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) {
+            const int q = gi[j] % w > 0 ? gi[j] - 1 : max(gi[j] - w, 0);  // left, or above
+            sz[j] = size[root[j] ? gi[j] : 0];
+            t[j] = comp[root[j] ? q : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < kPxPerThread; ++j) {
+            const int li = threadIdx.x + j * kBlock;
+            small[j] = root[j] && gi[j] != 0 && is_small(g, sz[j]);
             // link: a tile slot for a target inside the tile, -4 - target for
             // one outside, -1 for a surviving root, -2 for a pixel that is
             // not a root (never reached: targets are roots)
-            int l = root ? -1 : -2;
+            int l = root[j] ? -1 : -2;
             if (small[j]) {
                 const int ty = t[j] / w, tx = t[j] - ty * w;
                 const bool inside = tx >= x0 && tx < x0 + kTile && ty >= y0 && ty < y0 + kTile;
@@ -419,13 +429,17 @@ __global__ __launch_bounds__(kBlock) void ccl_merge_kernel(CclImage single, CclM
     gmem<int>* __restrict__ rank = as_global(g.rank);
     const int base = blk * kMergeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool survives[kMergePx];
+    bool survives[kMergePx], root[kMergePx];
 #pragma unroll
     for (int j = 0; j < kMergePx; ++j) {
         const int r = base + j * kBlock;
-        const int rc = min(r, n - 1);
-        const bool root = r < n && comp[rc] == r;
-        survives[j] = root && (r == 0 || !is_small(g, size[rc]));
+        root[j] = r < n && comp[min(r, n - 1)] == r;
+    }
+#pragma unroll
+    for (int j = 0; j < kMergePx; ++j) {
+        const int r = base + j * kBlock;
+        const int sz = size[root[j] ? r : 0];  // non-roots share one line
+        survives[j] = root[j] && (r == 0 || !is_small(g, sz));
     }
     unsigned long long ballot[kMergePx];
 #pragma unroll
