@@ -168,11 +168,14 @@ __device__ void lds_unite(int* P, int a, int b) {
 // 32-pixel tile rows; each pixel finds the head of its horizontal run of
 // equal labels from a ballot of run starts, and union-find then links run
 // heads only, once per vertical overlap of two runs.  Writes P[i] = global
-// index of i's local root, lroot[i] = its local index, and clears size[i].
+// index of i's local root and lroot[i] = its local index; a local root's
+// size entry receives the pixel count of its part of the tile (the run
+// lengths added per run head, far fewer LDS atomics than one per pixel).
 template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclMap map) {
     __shared__ int lab[kTilePx];
     __shared__ int par[kTilePx];
+    __shared__ int cnt[kTilePx];
     CclImage g;
     int bx, by;
     tile_of_launch<kBatch>(single, map, &g, &bx, &by);
@@ -195,16 +198,22 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
         const int li = threadIdx.x + j * kBlock;
         const int x = x0 + col, y = y0 + li / kTile;
         lab[li] = (x < w && y < h) ? v[j] : -1;
+        cnt[li] = 0;
     }
     __syncthreads();
-    // every pixel links to the head (first pixel) of its run
+    // every pixel links to the head (first pixel) of its run; a head also
+    // notes its run's length (up to the next run start of the row)
     const int half = (threadIdx.x & 63) >= 32 ? 32 : 0;  // which row of the wavefront
     const unsigned upto = col == 31 ? 0xFFFFFFFFu : (2u << col) - 1u;
+    int runlen[kPxPerThread];
+#pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
         const bool start = col == 0 || lab[li] != lab[li - 1];
         const unsigned row_starts = static_cast<unsigned>(__ballot(start) >> half);
         par[li] = li - col + (31 - __clz(row_starts & upto));
+        const unsigned later = row_starts & ~upto;  // starts right of this column
+        runlen[j] = start ? (later ? __ffs(later) - 1 : kTile) - col : 0;
     }
     __syncthreads();
     for (int j = 0; j < kPxPerThread; ++j) {
@@ -218,15 +227,26 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
         lds_unite(par, li, li - kTile);
     }
     __syncthreads();
+    int rr[kPxPerThread];
+#pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
         const int x = x0 + col, y = y0 + li / kTile;
+        rr[j] = -1;
         if (x >= w || y >= h) continue;
         const int r = lds_find(par, li);
+        rr[j] = r;
         const size_t gi = static_cast<size_t>(y) * w + x;
         P[gi] = (y0 + r / kTile) * w + x0 + r % kTile;
         lroot[gi] = r;
-        size[gi] = 0;
+        if (runlen[j] > 0) atomicAdd(cnt + r, runlen[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPxPerThread; ++j) {
+        const int li = threadIdx.x + j * kBlock;
+        if (rr[j] != li) continue;  // local roots only (pixels inside the image)
+        size[static_cast<size_t>(y0 + li / kTile) * w + x0 + col] = cnt[li];
     }
 }
 
@@ -254,24 +274,24 @@ __global__ __launch_bounds__(2 * kTile) void ccl_border_kernel(CclImage single, 
     }
 }
 
-// comp[i] = P[i] = root of i (the component's smallest index); the tile adds
-// its pixel count per local root to size[root].  Only the tile's local roots
-// walk the forest (the thread's walks advanced together, with unconditional
-// loads, so that they overlap); every pixel then takes its local root's
-// result from LDS.
+// comp[i] = P[i] = root of i (the component's smallest index).  Only the
+// tile's local roots walk the forest (the thread's walks advanced together,
+// with unconditional loads, so that they overlap); every pixel then takes
+// its local root's result from LDS.  A local root that is not its
+// component's root adds its part's pixel count (its size entry, from the
+// tile-local pass) to the root's entry, which holds the root's own part.
 template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, CclMap map) {
-    __shared__ int cnt[kTilePx];
     __shared__ int root[kTilePx];
     CclImage g;
     int bx, by;
     tile_of_launch<kBatch>(single, map, &g, &bx, &by);
     gmem<int>* P = as_global(g.comp);
     gmem<const int>* __restrict__ lroot = as_global(g.lroot);
-    gmem<int>* __restrict__ size = as_global(g.size);
+    gmem<int>* size = as_global(g.size);
     const int w = g.w, h = g.h;
     const int x0 = bx * kTile, y0 = by * kTile;
-    int lr[kPxPerThread], x[kPxPerThread];
+    int lr[kPxPerThread], x[kPxPerThread], self[kPxPerThread];
     bool in[kPxPerThread];
 #pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
@@ -279,10 +299,10 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
         const int px = x0 + li % kTile, py = y0 + li / kTile;
         in[j] = px < w && py < h;
         lr[j] = lroot[static_cast<size_t>(min(py, h - 1)) * w + min(px, w - 1)];
-        cnt[li] = 0;
         // a local root starts a walk from its own pixel; others stand on
         // pixel 0, which is always a root
-        x[j] = in[j] && lr[j] == li ? py * w + px : 0;
+        self[j] = in[j] && lr[j] == li ? py * w + px : 0;
+        x[j] = self[j];
     }
     unsigned live = 0u;
 #pragma unroll
@@ -302,24 +322,19 @@ __global__ __launch_bounds__(kBlock) void ccl_flatten_kernel(CclImage single, Cc
 #pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         const int li = threadIdx.x + j * kBlock;
-        if (in[j] && lr[j] == li) root[li] = x[j];
+        if (!(in[j] && lr[j] == li)) continue;
+        root[li] = x[j];
+        if (x[j] != self[j])  // pixel 0 is always its own root, so self 0 never adds
+            __hip_atomic_fetch_add(size + x[j], size[self[j]], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kPxPerThread; ++j) {
         if (!in[j]) continue;
         const int li = threadIdx.x + j * kBlock;
-        atomicAdd(cnt + lr[j], 1);
         const size_t gi = static_cast<size_t>(y0 + li / kTile) * w + x0 + li % kTile;
         __hip_atomic_store(P + gi, root[lr[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPxPerThread; ++j) {
-        const int li = threadIdx.x + j * kBlock;
-        const int c = cnt[li];
-        if (c > 0)
-            __hip_atomic_fetch_add(size + root[li], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
