@@ -51,6 +51,7 @@ def _load():
         "orc_seed": [_P, _P, _P, _I, _I, _I, _I, _P],
         "orc_assign": [_P, _P, _P, _I, _I, _I, _F, _P, _P],
         "orc_update": [_P, _P, _P, _I, _I, _P, _I, _P, _P],
+        "orc_update_votes": [_P, _P, _P, _I, _I, _P, _P, _I, _P, _P],
         "orc_kmeans": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _P, _P, _P],
         "orc_kmeans_ex": [_P, _P, _P, _I, _I, _I, _F, _I, _I, _I, _P, _P, _P],
         "orc_assign_ex": [_P, _P, _P, _I, _I, _I, _F, _I, _P, _P],
@@ -86,6 +87,8 @@ def _load():
     lib.orn_loss_grad.restype = ctypes.c_int
     lib.orn_decode.argtypes = [_I, _I, _I, _P, _P]
     lib.orn_decode.restype = ctypes.c_int
+    lib.orn_votes.argtypes = [_I, _I, _P, _D, _P]
+    lib.orn_votes.restype = ctypes.c_int
     lib.orn_targets.argtypes = [_I, _I, _I, _P, _P]
     lib.orn_targets.restype = ctypes.c_int
     _lib = lib
@@ -188,15 +191,23 @@ def assign(lab, S: int, m: float, centres: np.ndarray, dist: int = DIST_EQ1):
     return lab_out
 
 
-def update(lab, labels: np.ndarray, centres: np.ndarray):
-    """Section 3 centre update.  Returns (new centres (K,5), counts (K,))."""
+def update(lab, labels: np.ndarray, centres: np.ndarray, votes: np.ndarray | None = None):
+    """Section 3 centre update.  Returns (new centres (K,5), counts (K,)).
+    With ``votes`` (bool (H,W)) only the pixels where it is true count."""
     L, A, B = (np.ascontiguousarray(v, np.float32) for v in lab)
     h, w = L.shape
     cen = np.array(centres, np.float32, copy=True, order="C")
     cnt = np.empty(cen.shape[0], np.int32)
     lb = np.ascontiguousarray(labels, np.int32)
-    _check(_load().orc_update(_ptr(L), _ptr(A), _ptr(B), w, h, _ptr(lb), cen.shape[0],
-                              _ptr(cen), _ptr(cnt)), "update")
+    if votes is None:
+        _check(_load().orc_update(_ptr(L), _ptr(A), _ptr(B), w, h, _ptr(lb), cen.shape[0],
+                                  _ptr(cen), _ptr(cnt)), "update")
+    else:
+        vt = np.ascontiguousarray(votes, np.uint8)
+        if vt.shape != lb.shape:
+            raise ValueError("votes must have the labels' shape")
+        _check(_load().orc_update_votes(_ptr(L), _ptr(A), _ptr(B), w, h, _ptr(lb), _ptr(vt),
+                                        cen.shape[0], _ptr(cen), _ptr(cnt)), "update")
     return cen, cnt
 
 
@@ -357,6 +368,16 @@ def net_decode(logits, S: int):
     out = np.empty((h, w), np.int32)
     _check(_load().orn_decode(w, h, S, _ptr(lg), _ptr(out)), "net decode")
     return out
+
+
+def net_votes(logits, min_confidence: float):
+    """bool (H, W): the pixels whose best class has softmax probability at
+    least min_confidence (they alone vote in the warm start's first update)."""
+    lg = np.ascontiguousarray(logits, np.float64)
+    h, w, _ = lg.shape
+    out = np.empty((h, w), np.uint8)
+    _check(_load().orn_votes(w, h, _ptr(lg), float(min_confidence), _ptr(out)), "net votes")
+    return out.astype(bool)
 
 
 def net_targets(labels, S: int):

@@ -259,6 +259,25 @@ int orn_decode(int w, int h, int S, const double* logits, int32_t* labels) {
     return 0;
 }
 
+/* Which decoded pixels vote in the first centre update: those whose best
+ * class has softmax probability at least tau, i.e. sum_c exp(l_c - l_best)
+ * * tau <= 1 (FP64).  tau = 0: every pixel; tau > 1: none.  The others keep
+ * their decoded label but leave the first update to the confident pixels,
+ * whose colours are purer (a reading of the extension's decode, not a step
+ * of the paper). */
+int orn_votes(int w, int h, const double* logits, double tau, uint8_t* votes) {
+    if (w < 1 || h < 1 || !logits || !votes || !(tau >= 0.0)) return 1;
+    for (size_t i = 0; i < (size_t)w * h; i++) {
+        const double* l = logits + i * C3;
+        int best = 0;
+        for (int c = 1; c < C3; c++) if (l[c] > l[best]) best = c;
+        double s = 0.0;
+        for (int c = 0; c < C3; c++) s += exp(l[c] - l[best]);
+        votes[i] = s * tau <= 1.0;
+    }
+    return 0;
+}
+
 /* Training target: the class of the cell holding the pixel's label relative
  * to the pixel's own cell, (dy+1)*3 + (dx+1); -1 if it is not a neighbour. */
 int orn_targets(int w, int h, int S, const int32_t* labels, int32_t* target) {

@@ -371,10 +371,13 @@ int orc_assign(const float* L, const float* A, const float* B, int32_t w, int32_
  * (round half to even); x, y are integers already.  Sums are int64, so any
  * order of summation gives the same result.  The mean is the FP64 quotient
  * sum/count, scaled back by 2^-18 and rounded to FP32.  A centre with no
- * pixels keeps its previous value.
+ * pixels keeps its previous value.  votes: NULL, or only the pixels with
+ * votes[i] != 0 are counted (the learned warm start's first update takes
+ * its confident pixels this way); every label must still be a cluster.
  * ---------------------------------------------------------------------- */
-int orc_update(const float* L, const float* A, const float* B, int32_t w, int32_t h,
-               const int32_t* labels, int32_t K, float* centres, int32_t* counts) {
+int orc_update_votes(const float* L, const float* A, const float* B, int32_t w, int32_t h,
+                     const int32_t* labels, const uint8_t* votes, int32_t K, float* centres,
+                     int32_t* counts) {
     if (!L || !A || !B || !labels || !centres || !counts || w < 1 || h < 1 || K < 1)
         return ORC_EINVAL;
     int64_t* sums = (int64_t*)calloc((size_t)K * 5, sizeof(int64_t));
@@ -389,6 +392,7 @@ int orc_update(const float* L, const float* A, const float* B, int32_t w, int32_
                 free(sums);
                 return ORC_EINVAL;
             }
+            if (votes && !votes[i]) continue;
             int64_t* s = sums + 5 * (size_t)k;
             s[0] += llrintf(L[i] * scale);
             s[1] += llrintf(A[i] * scale);
@@ -413,6 +417,11 @@ int orc_update(const float* L, const float* A, const float* B, int32_t w, int32_
     }
     free(sums);
     return ORC_OK;
+}
+
+int orc_update(const float* L, const float* A, const float* B, int32_t w, int32_t h,
+               const int32_t* labels, int32_t K, float* centres, int32_t* counts) {
+    return orc_update_votes(L, A, B, w, h, labels, NULL, K, centres, counts);
 }
 
 /* ------------------------------------------------------------------------

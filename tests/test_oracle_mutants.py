@@ -48,6 +48,7 @@ MUTANTS = [
      ["update"]),
     ("loop_extra_round", "for (int32_t it = 0; it < iters; it++)",
      "for (int32_t it = 0; it <= iters; it++)", ["update"]),
+    ("update_votes_ignored", "if (votes && !votes[i]) continue;", "", ["votes"]),
     ("ccl_join_direction", "size_t q = x > 0 ? r - 1 : r - (size_t)w;",
      "size_t q = x > 0 ? r - (size_t)w : r - 1;", ["ccl"]),
     ("ccl_threshold", "(int64_t)4 * size[r] < (int64_t)S * (int64_t)S",
@@ -70,6 +71,11 @@ NET_MUTANTS = [
      "d[c] = (pr - (c == target[i] ? 0.5 : 0.0))", ["net"]),
     ("net_input_scale", "n->x[3 * i + 1] = rnd(bf, (double)(A[i] / 128.0f));",
      "n->x[3 * i + 1] = rnd(bf, (double)(A[i] / 100.0f));", ["net"]),
+    ("votes_direction", "votes[i] = s * tau <= 1.0;", "votes[i] = s * tau >= 1.0;", ["net"]),
+    ("votes_reference_class", "for (int c = 0; c < C3; c++) s += exp(l[c] - l[best]);",
+     "for (int c = 0; c < C3; c++) s += exp(l[c] - l[0]);", ["net"]),
+    ("votes_dropped_term", "for (int c = 0; c < C3; c++) s += exp(l[c] - l[best]);",
+     "for (int c = 1; c < C3; c++) s += exp(l[c] - l[best]);", ["net"]),
 ]
 
 PINS = {
@@ -88,7 +94,11 @@ PINS = {
                tu.test_zero_iterations_is_one_association_with_the_seeds,
                lambda: tu.test_uniform_image_centres_land_on_cell_middles(15, 9, 3)],
     "net": [lambda: [tn.test_backward_matches_central_differences(s) for s in range(2)],
-            lambda: [tn.test_forward_matches_scipy_correlation(s) for s in range(2)]],
+            lambda: [tn.test_forward_matches_scipy_correlation(s) for s in range(2)],
+            lambda: [tn.test_votes_closed_form(t) for t in (0.2, 0.5, 0.7, 0.9)],
+            tn.test_votes_against_softmax],
+    "votes": [lambda: [tu.test_update_over_voting_pixels_is_their_exact_mean(s)
+                       for s in range(3)]],
     "variants": [tv.test_xyz_white_black_grey, tv.test_xyz_is_additive_over_the_primaries,
                  lambda: [tv.test_squared_association_is_the_nearest_candidate(m)
                           for m in (10.0, 40.0)],

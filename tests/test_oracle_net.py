@@ -138,3 +138,33 @@ def test_decode_clamps_at_the_border():
     lg = np.zeros((4, 4, 9))
     lg[..., 0] = 1.0  # up-left of cell (0, 0) does not exist
     assert np.all(oracle.net_decode(lg, S) == 0)
+
+
+@pytest.mark.parametrize("tau", [0.2, 0.5, 0.7, 0.9])
+def test_votes_closed_form(tau):
+    """One class a above eight equal others: its softmax probability is
+    e^a / (e^a + 8), at least tau exactly when a >= ln(8 tau / (1 - tau)),
+    wherever the class sits and whatever the common offset."""
+    edge = math.log(8 * tau / (1 - tau))
+    rng = np.random.default_rng(int(tau * 10))
+    h, w = 4, 9
+    lg = np.zeros((h, w, 9))
+    lg += rng.uniform(-3, 3, (h, w, 1))  # common offset: softmax ignores it
+    best = rng.integers(0, 9, (h, w))
+    lift = np.where(np.arange(w)[None, :] % 2 == 0, edge + 1e-7, edge - 1e-7) * np.ones((h, 1))
+    lg[np.arange(h)[:, None], np.arange(w)[None, :], best] += lift
+    want = np.arange(w)[None, :] % 2 == 0
+    assert np.array_equal(oracle.net_votes(lg, tau), np.broadcast_to(want, (h, w)))
+
+
+def test_votes_against_softmax():
+    from scipy.special import softmax
+    rng = np.random.default_rng(7)
+    lg = rng.normal(0, 2, (30, 40, 9))
+    pmax = softmax(lg, axis=-1).max(-1)
+    for tau in (0.15, 0.3, 0.5, 0.8):
+        got = oracle.net_votes(lg, tau)
+        clear = np.abs(pmax - tau) > 1e-12
+        assert np.array_equal(got[clear], pmax[clear] >= tau)
+    assert oracle.net_votes(lg, 0.0).all()
+    assert not oracle.net_votes(lg, 1.01).any()

@@ -43,6 +43,37 @@ def test_update_is_the_exact_mean(seed):
         assert cen[k, 4] == np.float32(float(Fraction(int(y[sel].sum()), int(sel.sum()))))
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_update_over_voting_pixels_is_their_exact_mean(seed):
+    """The warm start's first update: only pixels with a vote count; a
+    cluster without one keeps its centre; all votes give the plain update."""
+    rng = np.random.default_rng(50 + seed)
+    h, w, S = 11, 14, 3
+    lab = tuple(rng.normal(40, 30, (h, w)).astype(np.float32) for _ in range(3))
+    _, nc, nr = oracle.grid(w, h, S)
+    K = nc * nr
+    labels = rng.integers(0, K, (h, w)).astype(np.int32)
+    votes = rng.random((h, w)) < 0.4
+    old = rng.normal(0, 1, (K, 5)).astype(np.float32)
+    cen, cnt = oracle.update(lab, labels, old, votes)
+    assert np.array_equal(cnt, np.bincount(labels[votes], minlength=K))
+    y, x = np.mgrid[0:h, 0:w]
+    for k in range(K):
+        sel = (labels == k) & votes
+        if not sel.any():
+            assert np.array_equal(cen[k], old[k])
+            continue
+        for j in range(3):
+            assert cen[k, j] == _exact_centre(lab[j][sel], Q)
+        assert cen[k, 3] == np.float32(float(Fraction(int(x[sel].sum()), int(sel.sum()))))
+        assert cen[k, 4] == np.float32(float(Fraction(int(y[sel].sum()), int(sel.sum()))))
+    all_c, all_n = oracle.update(lab, labels, old, np.ones((h, w), bool))
+    plain_c, plain_n = oracle.update(lab, labels, old)
+    assert np.array_equal(all_c, plain_c) and np.array_equal(all_n, plain_n)
+    none_c, none_n = oracle.update(lab, labels, old, np.zeros((h, w), bool))
+    assert np.array_equal(none_c, old) and not none_n.any()
+
+
 def test_fixed_point_rounds_half_to_even():
     # 2^-19 and 3*2^-19 are exactly halfway between fixed-point steps
     h, w = 1, 2
