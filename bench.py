@@ -255,19 +255,51 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
+    tau, validation = c5_pick_confidence(slic, torch, dev, net, n_train, 8)
     result = {"images": n_eval, "S": S,
               "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
                         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
                         "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
-                        "loss": [[s, round(v, 4)] for s, v in log]}}
-    result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False))
-    result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True)
+                        "loss": [[s, round(v, 4)] for s, v in log]},
+              "min_confidence": tau,
+              "validation": {"images": "8 held-out training images (640x480)",
+                             "energy_ratio_mean_2_rounds_by_min_confidence": validation}}
+    result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False, tau=tau))
+    result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True, tau=tau)
     return result
 
 
-def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool):
+C5_CONFIDENCES = (0.0, 0.5, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85)
+
+
+def c5_pick_confidence(slic, torch, dev, net, first: int, n_val: int):
+    """The decode's minimum confidence with the lowest mean energy ratio
+    (2 warm rounds against plain 10 rounds) on training-distribution images
+    the net never saw (training images first .. first + n_val - 1)."""
+    import synth
+    from synth.configs import warm_train_workload
+    S = net.S
+    vals = [warm_train_workload(first + j) for j in range(n_val)]
+    imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in vals]
+    params = [slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb) for w in vals]
+    plain = [float(slic.segment(r, p, 10, want_energy=True)["energy"].cpu()[0])
+             for r, p in zip(imgs, params)]
+    table = {}
+    for tau in C5_CONFIDENCES:
+        prepared = slic.warm.prepare(net.params, S, tau)
+        ratios = [float(slic.warm.warm_segment(r, p, prepared, 2)["energy"].cpu()[0]) / e
+                  for r, p, e in zip(imgs, params, plain)]
+        table[str(tau)] = round(sum(ratios) / len(ratios), 4)
+    best = min(C5_CONFIDENCES, key=lambda t: table[str(t)])
+    return best, table
+
+
+def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, tau: float):
     """The trained net against plain SLIC on ``n_eval`` evaluation images of
-    640x480 (or 1920x1080 with ``hd``), one image at a time."""
+    640x480 (or 1920x1080 with ``hd``), one image at a time, with the
+    decode's minimum confidence ``tau``; then the warm start at 2..4 rounds
+    beside plain SLIC after as many associations (one round fewer), and the
+    plain argmax decode (every pixel votes) at 2 rounds."""
     import numpy as np
 
     import synth
@@ -293,13 +325,19 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool):
                               None, e_plain[i:].data_ptr() if with_energy else None, None, stream,
                               ws_plain.data_ptr(), ws_plain.numel())
 
-    prepared = slic.warm.prepare(net.params, S)
+    prepared = slic.warm.prepare(net.params, S, tau)
 
-    def run_warm():
+    def run_warm(rounds=warm_iters, net_buf=prepared, out=e_warm):
         for i in range(n_eval):
-            slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), prepared.data_ptr(), warm_iters,
-                                   0, lab_warm[i].data_ptr(), None, e_warm[i:].data_ptr(), None,
+            slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), net_buf.data_ptr(), rounds,
+                                   0, lab_warm[i].data_ptr(), None, out[i:].data_ptr(), None,
                                    stream, ws_warm.data_ptr(), ws_warm.numel())
+
+    def run_plain_n(rounds, out):
+        for i in range(n_eval):
+            slic.slic_segment(cps[i], imgs[i].data_ptr(), rounds, 0, lab_plain[i].data_ptr(), None,
+                              out[i:].data_ptr(), None, stream, ws_plain.data_ptr(),
+                              ws_plain.numel())
 
     def timed(fn):
         fn()
@@ -324,13 +362,34 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool):
     agree = [float((a == b).float().mean()) for a, b in zip(lab_warm, lab_plain)]
     # plain energies at the warm start's iteration count, for the gain
     e2 = torch.empty(n_eval, dtype=torch.float64, device=dev)
-    for i in range(n_eval):
-        slic.slic_segment(cps[i], imgs[i].data_ptr(), warm_iters, 0, lab_plain[i].data_ptr(), None,
-                          e2[i:].data_ptr(), None, stream, ws_plain.data_ptr(), ws_plain.numel())
+    run_plain_n(warm_iters, e2)
     e2 = e2.cpu().numpy()
     t_charged = t_warm + t_plain * float((~passed).sum()) / n_eval
+    # more warm rounds, against plain SLIC after as many associations
+    sweep = {}
+    e_tmp = torch.empty(n_eval, dtype=torch.float64, device=dev)
+    for rounds in (2, 3, 4):
+        t_r = timed(lambda: run_warm(rounds, prepared, e_tmp))
+        run_warm(rounds, prepared, e_tmp)
+        r_w = e_tmp.cpu().numpy() / ep
+        run_plain_n(rounds - 1, e_tmp)
+        r_p = e_tmp.cpu().numpy() / ep
+        run_plain_n(rounds, e_tmp)
+        r_same = e_tmp.cpu().numpy() / ep
+        sweep[str(rounds)] = {
+            "plain_same_rounds_energy_ratio_mean": round(float(r_same.mean()), 4),
+            "plain_same_rounds_gate_pass_rate": round(float((r_same <= 1.01).mean()), 4),
+            "warm_frames_per_s": round(n_eval / t_r, 1),
+            "energy_ratio_mean": round(float(r_w.mean()), 4),
+            "energy_ratio_max": round(float(r_w.max()), 4),
+            "gate_pass_rate": round(float((r_w <= 1.01).mean()), 4),
+            "plain_equal_associations_energy_ratio_mean": round(float(r_p.mean()), 4),
+            "warm_below_plain_equal_associations": int((r_w < r_p).sum())}
+    argmax_net = slic.warm.prepare(net.params, S, 0.0)
+    run_warm(warm_iters, argmax_net, e_tmp)
+    r_argmax = e_tmp.cpu().numpy() / ep
     w0 = evals[0]
-    return {"size": f"{w0.width}x{w0.height}",
+    return {"size": f"{w0.width}x{w0.height}", "min_confidence": tau,
             "plain_iters": plain_iters, "warm_iters": warm_iters,
             "plain_frames_per_s": round(n_eval / t_plain, 1),
             "warm_frames_per_s": round(n_eval / t_warm, 1),
@@ -340,7 +399,9 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool):
             "energy_ratio_max": round(float(ratio.max()), 4),
             "plain_2iter_energy_ratio_mean": round(float((e2 / ep).mean()), 4),
             "warm_below_plain_2iter": int((ew < e2).sum()),
-            "label_agreement_mean": round(float(np.mean(agree)), 4)}
+            "label_agreement_mean": round(float(np.mean(agree)), 4),
+            "argmax_decode_energy_ratio_mean": round(float(r_argmax.mean()), 4),
+            "rounds": sweep}
 
 
 def bench_video(slic, torch, dev, n_frames: int, rounds: int, reps: int):

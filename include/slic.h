@@ -297,13 +297,20 @@ int slic_net_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, 
                   int32_t step, float lr, float beta1, float beta2, float eps, void* hip_stream);
 
 /* A prepared net for inference: the bf16 weight copies in the layouts the
- * kernels read, followed by the FP32 parameters.  slic_net_prepared_bytes
- * is the size of that device buffer (the same for every S; it must be
- * 256-byte aligned); slic_net_prepare fills it from d_params
- * (slic_net_param_count(S) floats, enqueued on the stream).  Prepare once
- * per parameter set, then run any number of frames with the same step S. */
+ * kernels read, followed by the FP32 parameters and the decode's minimum
+ * confidence.  slic_net_prepared_bytes is the size of that device buffer
+ * (the same for every S; it must be 256-byte aligned); slic_net_prepare
+ * fills it from d_params (slic_net_param_count(S) floats, enqueued on the
+ * stream).  min_confidence (finite, >= 0): only pixels whose best class
+ * has softmax probability >= min_confidence vote in the first centre update
+ * of a warm start (0: every pixel; above 1: none, so the first update
+ * keeps the seeds); every pixel still carries its decoded label.  Prepare
+ * once per parameter set, then run any number of frames with the same step
+ * S.  SLIC_EINVAL for S outside 1..32, a negative, NaN or infinite
+ * min_confidence, or a missing or misaligned buffer. */
 size_t slic_net_prepared_bytes(void);
-int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_stream);
+int slic_net_prepare(int32_t S, const float* d_params, float min_confidence, void* d_net,
+                     void* hip_stream);
 
 /* Warm-started segmentation.  slic_warm_init converts d_rgb, seeds the
  * centres exactly as slic_init does, runs the prepared net d_net (prepared
@@ -311,7 +318,8 @@ int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_st
  * and takes its decoded label map as the first association (in place of
  * slic_init's association with the seeds).  The context then behaves as one
  * from slic_init: slic_iterate(ctx, n) runs n rounds of (update,
- * associate), the first update using the net's labels; a cluster that no
+ * associate), the first update using the net's labels of the pixels that
+ * vote (the prepared net's minimum confidence); a cluster that no voting
  * pixel chose keeps its seed.  Workspace: slic_warm_workspace_bytes(p)
  * (equal to slic_workspace_bytes(p); 0 if S is beyond the net's range).
  * slic_warm_segment runs init, n_iters rounds, the energy (d_energy may be

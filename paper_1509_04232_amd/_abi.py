@@ -88,7 +88,7 @@ _SIGS = {
     "slic_net_adam": ([_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                        ctypes.c_float, _P], ctypes.c_int),
     "slic_net_prepared_bytes": ([], ctypes.c_size_t),
-    "slic_net_prepare": ([_I, _P, _P, _P], ctypes.c_int),
+    "slic_net_prepare": ([_I, _P, ctypes.c_float, _P, _P], ctypes.c_int),
     "slic_warm_workspace_bytes": ([_PP], ctypes.c_size_t),
     "slic_warm_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_warm_segment": ([_PP, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t],
@@ -328,8 +328,9 @@ def slic_net_prepared_bytes() -> int:
     return int(lib.slic_net_prepared_bytes())
 
 
-def slic_net_prepare(S: int, d_params: int, d_net: int, stream: int) -> None:
-    _check(lib.slic_net_prepare(S, d_params, d_net, stream), "slic_net_prepare")
+def slic_net_prepare(S: int, d_params: int, min_confidence: float, d_net: int,
+                     stream: int) -> None:
+    _check(lib.slic_net_prepare(S, d_params, min_confidence, d_net, stream), "slic_net_prepare")
 
 
 def slic_warm_workspace_bytes(p: SlicParams) -> int:

@@ -87,9 +87,10 @@ struct NetWeights {
 // ------------------------------------------------------------- weights
 
 __global__ void prepare_kernel(const float* __restrict__ p, NetWeights wt, int count,
-                               float* __restrict__ copy) {
+                               float* __restrict__ copy, float* conf_out, float conf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (copy && i < count) copy[i] = p[i];
+    if (conf_out && i == 0) *conf_out = conf;
     if (i >= 9 * kC * kC) return;
     const int t = i / (kC * kC), o = (i / kC) % kC, c = i % kC;
     wt.W1b[i] = c < 3 ? bf16_bits(p[kOffW1 + (t * kC + o) * 3 + c]) : 0;
@@ -538,8 +539,9 @@ __global__ void export_logits_kernel(const float* __restrict__ lg16, long long t
 // + gridDim.x, ...  The logits stay in registers: the argmax combines the
 // four lanes that hold a pixel's classes, and the decoded label enters the
 // cluster sums as in the association kernel (LDS bins, then one global add
-// per non-empty bin); the workgroup holding a cell's first pixel clears that
-// cluster's next accumulator.
+// per non-empty bin) if the pixel votes (its best class's softmax
+// probability reaches the prepared minimum confidence); the workgroup
+// holding a cell's first pixel clears that cluster's next accumulator.
 constexpr int kFW = 32, kFH = 8;
 constexpr int kXW = kFW + 6, kXH = kFH + 6;      // input region
 constexpr int kA1W = kFW + 4, kA1H = kFH + 4;    // first hidden layer region
@@ -562,6 +564,7 @@ struct FusedImage {
     const float *L, *A, *B;
     int w, h, S, ns_c, ns_r;
     const float *b1, *b2, *b3, *P;
+    const float* conf;  // minimum softmax probability of a voting pixel
     int32_t* labels;
     long long *sums_acc, *sums_next;
     int tiles_x, n_tiles;
@@ -616,6 +619,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
     const int t0 = 2 * kq, t1 = 2 * kq + 1;
     const int xoff0 = ((t0 / 3) * kXW + t0 % 3) * 4, xoff1 = ((t1 / 3) * kXW + t1 % 3) * 4;
     const float scale = static_cast<float>(1 << kQShift);
+    const float tau = *g.conf;
 
     // the input region of a tile, loaded one tile ahead so that its latency
     // overlaps the previous tile's work (zeros outside the image)
@@ -831,11 +835,22 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
                     bc = oc;
                 }
             }
+            // the pixel's best class has softmax probability 1 / se; it votes
+            // in the first update when that reaches the minimum confidence
+            float se = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = kq * 4 + i;
+                if (o < kC3) se += __expf(accs[u][i] + pb[u][i] - bv);
+            }
+            se += __shfl_xor(se, 16);
+            se += __shfl_xor(se, 32);
             if (kq == 0 && x < g.w && y < g.h) {
                 const int cy = min(max(tab[2 * kFW + r] + bc / 3 - 1, 0), g.ns_r - 1);
                 const int cx = min(max(tab[c] + bc % 3 - 1, 0), g.ns_c - 1);
                 const size_t pi = static_cast<size_t>(y) * g.w + x;
                 g.labels[pi] = cy * g.ns_c + cx;
+                if (!(se * tau <= 1.0f)) continue;
                 const int cell = (cy - gy_lo) * ncx + (cx - gx_lo);
                 const float* lab = slab + p * 3;
                 atomicAdd(bins + cell, static_cast<unsigned long long>(
@@ -968,7 +983,8 @@ hipError_t enqueue_forward(const NetWs& nw, const CropTable& ct, int n, int cw, 
                            const float* params, hipStream_t s) {
     {
         KernelTimer t("net_prepare", s);
-        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt, 0, nullptr);
+        prepare_kernel<<<(9 * kC * kC + 255) / 256, 256, 0, s>>>(params, nw.wt, 0, nullptr,
+                                                                  nullptr, 0.0f);
     }
     const int per = cw * ch;
     {
@@ -1059,7 +1075,8 @@ hipError_t enqueue_backward(const NetWs& nw, const CropTable& ct, int n, int cw,
 }  // namespace
 
 // A prepared net: the bf16 weight copies followed by the FP32 parameter
-// vector, sized for the largest S so that a phase index never leaves it.
+// vector, sized for the largest S so that a phase index never leaves it,
+// and then the decode's minimum confidence (one float).
 constexpr int kMaxParams = kOffP + kC3 * kMaxS * kMaxS;
 
 size_t prepared_layout(NetWeights* wt, float** params, char* base) {
@@ -1067,7 +1084,7 @@ size_t prepared_layout(NetWeights* wt, float** params, char* base) {
     const size_t off = net_layout(1, 1, 1, 1, kWeights, &nw, base);
     if (wt) *wt = nw.wt;
     if (params) *params = base ? reinterpret_cast<float*>(base + off) : nullptr;
-    return off + align_up(static_cast<size_t>(kMaxParams) * sizeof(float));
+    return off + align_up(static_cast<size_t>(kMaxParams + 1) * sizeof(float));
 }
 
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
@@ -1080,7 +1097,7 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
     const int n_tiles = tiles_x * ((h + kFH - 1) / kFH);
     FusedImage f{ws.L, ws.A, ws.B, w, h, g.S, g.ns_c, g.ns_r,
                  params + kOffB1, params + kOffB2, params + kOffB3, params + kOffP,
-                 ws.labels, ws.sums, ws.sums + ring, tiles_x, n_tiles};
+                 params + kMaxParams, ws.labels, ws.sums, ws.sums + ring, tiles_x, n_tiles};
     // persistent workgroups: two per compute unit (their LDS fits twice)
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1110,8 +1127,10 @@ extern "C" {
 
 size_t slic_net_prepared_bytes(void) { return prepared_layout(nullptr, nullptr, nullptr); }
 
-int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_stream) {
-    if (S < 1 || S > kMaxS || !device_ptr(d_params) || !device_ptr(d_net) ||
+int slic_net_prepare(int32_t S, const float* d_params, float min_confidence, void* d_net,
+                     void* hip_stream) {
+    if (S < 1 || S > kMaxS || !(min_confidence >= 0.0f) || !std::isfinite(min_confidence) ||
+        !device_ptr(d_params) || !device_ptr(d_net) ||
         reinterpret_cast<uintptr_t>(d_net) % kAlign != 0)
         return SLIC_EINVAL;
     NetWeights wt;
@@ -1120,7 +1139,8 @@ int slic_net_prepare(int32_t S, const float* d_params, void* d_net, void* hip_st
     const int count = kOffP + kC3 * S * S;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int n = count > 9 * kC * kC ? count : 9 * kC * kC;
-    prepare_kernel<<<(n + 255) / 256, 256, 0, s>>>(d_params, wt, count, params);
+    prepare_kernel<<<(n + 255) / 256, 256, 0, s>>>(d_params, wt, count, params,
+                                                   params + kMaxParams, min_confidence);
     return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
 }
 

@@ -125,16 +125,20 @@ class Net:
         return loss
 
 
-def prepare(params: torch.Tensor, S: int, stream=None, out: torch.Tensor | None = None):
+def prepare(params: torch.Tensor, S: int, min_confidence: float = 0.0, stream=None,
+            out: torch.Tensor | None = None):
     """slic_net_prepare: the inference copy of a parameter vector (a uint8
-    device tensor of slic_net_prepared_bytes())."""
+    device tensor of slic_net_prepared_bytes()).  Only pixels whose best
+    class has softmax probability >= min_confidence vote in the warm
+    start's first centre update (0: all)."""
     if params.dtype != torch.float32 or params.device.type != "cuda":
         raise ValueError("params must be a float32 GPU tensor")
     if params.numel() != _abi.slic_net_param_count(S):
         raise ValueError(f"expected {_abi.slic_net_param_count(S)} parameters for S={S}")
     net = out if out is not None else torch.empty(_abi.slic_net_prepared_bytes(),
                                                   dtype=torch.uint8, device=params.device)
-    _abi.slic_net_prepare(S, params.data_ptr(), net.data_ptr(), _stream(stream))
+    _abi.slic_net_prepare(S, params.data_ptr(), float(min_confidence), net.data_ptr(),
+                          _stream(stream))
     return net
 
 

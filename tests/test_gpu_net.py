@@ -2,8 +2,8 @@
 loss gradient (relative L2 error at most 1e-2, the scale of bfloat16
 rounding of activations), training targets (exact), the Adam step (its
 definition in float64), and the warm-started segmentation against the
-oracle's composition of seeding, decoding and (update, associate) rounds
-(exact labels and centres)."""
+oracle's composition of seeding, decoding, the confidence votes of the
+first update and (update, associate) rounds (exact labels and centres)."""
 import numpy as np
 import pytest
 import torch
@@ -205,6 +205,67 @@ def test_warm_segment_matches_oracle(slic, w, h, S, perturb, iters):
     assert float(out["energy"].cpu()[0]) == pytest.approx(energy, rel=1e-9)
 
 
+def _two_level_params(S, seed):
+    """Like _decisive_params, but at every other phase the leading class is
+    only 2.5 above the rest: those pixels' best class is far less probable,
+    so a confidence threshold splits the pixels with a wide margin."""
+    p = _decisive_params(S, seed)
+    off = oracle.net_offsets(S)
+    P = p[off["P"]:off["end"]].reshape(S * S, 9)
+    P[1::2] = np.where(P[1::2] == 5.0, 2.5, P[1::2])
+    return p
+
+
+@pytest.mark.parametrize("w,h,S,perturb,iters", [
+    (97, 61, 8, True, 2), (130, 77, 5, False, 3), (64, 64, 16, True, 1), (150, 90, 8, True, 0),
+    (33, 17, 4, True, 4)])
+def test_warm_segment_with_votes_matches_oracle(slic, w, h, S, perturb, iters):
+    """A minimum confidence between the two levels: only the confident
+    pixels vote in the first update, exactly as the oracle's composition
+    (decode, votes, update over the voters, then plain rounds)."""
+    img, lab = _image(w, h, 40 + S)
+    p = _two_level_params(S, 50 + w)
+    lg, _, _ = oracle.net_forward(lab, p.astype(np.float64), S, True)
+    top2 = np.sort(lg, axis=-1)[..., -2:]
+    assert (top2[..., 1] - top2[..., 0]).min() > 1.0
+    log_se = np.log(np.exp(lg - lg.max(-1, keepdims=True)).sum(-1))
+    cut = 0.2  # the votes' threshold in log-mass: tau = exp(-cut)
+    assert np.abs(log_se - cut).min() > 0.05  # no pixel near it
+    tau = float(np.exp(-cut))
+    votes = oracle.net_votes(lg, tau)
+    assert 0.2 < votes.mean() < 0.8
+    labels = oracle.net_decode(lg, S)
+    cen = oracle.seed(lab, S, perturb)
+    for it in range(iters):
+        cen, _ = oracle.update(lab, labels, cen, votes if it == 0 else None)
+        labels = oracle.assign(lab, S, 10.0, cen)
+    energy = oracle.energy(lab, S, 10.0, cen, labels)
+
+    prm = slic.Params(w, h, S=S, m=10.0, perturb=perturb)
+    net = slic.warm.prepare(_dev(p), S, tau)
+    out = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, net, iters, want_centres=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["labels"].cpu().numpy(), labels)
+    assert np.array_equal(out["centres"].cpu().numpy(), cen)
+    assert float(out["energy"].cpu()[0]) == pytest.approx(energy, rel=1e-9)
+
+
+@pytest.mark.parametrize("w,h,S,seed", [(97, 61, 8, 0), (200, 130, 16, 1), (45, 33, 3, 2)])
+def test_warm_start_without_voters_is_plain_slic_one_round_shorter(slic, w, h, S, seed):
+    """Above 1 no pixel is confident enough: the first update keeps every
+    seed, so n warm rounds equal plain SLIC's n - 1 rounds exactly."""
+    img, _ = _image(w, h, 70 + seed)
+    rgb = _dev(img.reshape(-1))
+    prm = slic.Params(w, h, S=S, m=10.0)
+    net = slic.warm.prepare(_dev(_random_params(S, 75 + seed)), S, 1.5)
+    for n in (1, 2, 3):
+        warm = slic.warm.warm_segment(rgb, prm, net, n, want_centres=True)
+        plain = slic.segment(rgb, prm, n - 1, want_centres=True, want_energy=True)
+        assert torch.equal(warm["labels"], plain["labels"])
+        assert torch.equal(warm["centres"], plain["centres"])
+        assert torch.equal(warm["energy"], plain["energy"])
+
+
 @pytest.mark.parametrize("w,h,S,seed", [(97, 61, 8, 0), (200, 130, 16, 1), (45, 33, 3, 2)])
 def test_fused_decode_matches_oracle_away_from_ties(slic, w, h, S, seed):
     """Full random weights: the fused net's decoded labels (zero rounds)
@@ -277,6 +338,10 @@ def test_net_rejects_bad_arguments(slic):
         slic.warm.warm_segment(rgb, prm, torch.zeros(_abi.slic_net_prepared_bytes(),
                                                      dtype=torch.uint8), 2)
     with pytest.raises(_abi.SlicError):  # S beyond the phase table
-        _abi.slic_net_prepare(33, net.params.data_ptr(), net.ws.data_ptr(), 0)
+        _abi.slic_net_prepare(33, net.params.data_ptr(), 0.0, net.ws.data_ptr(), 0)
     with pytest.raises(ValueError):  # parameter count of another S
         slic.warm.prepare(net.params, 16)
+    buf = torch.empty(_abi.slic_net_prepared_bytes(), dtype=torch.uint8, device="cuda")
+    for bad in (-0.1, float("nan"), float("inf")):  # minimum confidence
+        with pytest.raises(_abi.SlicError):
+            slic.warm.prepare(net.params, 8, bad, out=buf)

@@ -1,8 +1,9 @@
 """Training of the warm-start net on the GPU (targets from plain SLIC's
 labels after 10 rounds, crops of c5 training images): the loss falls, the
 trained net predicts the converged cells better than the best predictor
-that sees only the grid phase (measured on the same image), and its warm
-start beats the untrained net's at equal rounds.  The gate falls back to
+that sees only the grid phase (measured on the same image), its warm start
+beats the untrained net's at equal rounds, and, with the first update over
+its confident pixels, plain SLIC's after as many associations.  The gate falls back to
 plain SLIC whenever the warm energy exceeds 1.01 times plain's."""
 import numpy as np
 import pytest
@@ -86,6 +87,22 @@ def test_training_improves_the_warm_start(slic, trained):
         e_t = float(slic.warm.warm_segment(rgb, p, trained_net, 2)["energy"].cpu()[0])
         e_u = float(slic.warm.warm_segment(rgb, p, untrained_net, 2)["energy"].cpu()[0])
         assert e_t < e_u, (e_t, e_u)
+
+
+def test_confident_warm_start_beats_the_grid_seeds(slic, trained):
+    """What the trained net gains over plain SLIC: with the first update
+    taken over its confident pixels (best class at least 70% probable), two
+    warm rounds end below plain SLIC after the same number of associations
+    (the seeds' association and one round), on images it never saw."""
+    net, _, _ = trained
+    prepared = slic.warm.prepare(net.params, S, 0.7)
+    for j in range(2):
+        wl = warm_eval_workload(j)
+        rgb = _rgb(wl)
+        p = slic.Params(wl.width, wl.height, S=S, m=wl.m, perturb=wl.perturb)
+        e_w = float(slic.warm.warm_segment(rgb, p, prepared, 2)["energy"].cpu()[0])
+        e_p = float(slic.segment(rgb, p, 1, want_energy=True)["energy"].cpu()[0])
+        assert e_w < e_p, (e_w, e_p)
 
 
 def test_gate_falls_back_to_plain(slic, trained):
