@@ -630,10 +630,15 @@ bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S) {
 
 int assign_default_variant(int32_t w, int32_t h, int32_t S) {
     const long long n = static_cast<long long>(w) * h;
-    // small frames are latency bound: the most workgroups; large frames
-    // amortise the staged centres over more pixels per thread
+    // small frames are latency bound: the most workgroups; larger frames
+    // amortise the staged centres over more pixels per thread (the
+    // autotuner's picks: 1 at 320x240, 4 at 640x480, 5 at 1920x1080); a
+    // shape the step or width does not allow falls back down the table
     int v = 1;
-    if (n >= (1ll << 20)) v = assign_variant_supported(4, w, h, S) ? 4 : 2;
+    if (n >= (1ll << 20))
+        v = 5;
+    else if (n >= (1ll << 17))
+        v = 4;
     while (v > 1 && !assign_variant_supported(v, w, h, S)) --v;
     return v;
 }
