@@ -255,27 +255,30 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    tau, validation = c5_pick_confidence(slic, torch, dev, net, n_train, 8)
+    taus, validation = c5_pick_confidence(slic, torch, dev, net, n_train, 8, (2, 3, 4))
+    tau = taus[2]
     result = {"images": n_eval, "S": S,
               "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
                         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
                         "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
                         "loss": [[s, round(v, 4)] for s, v in log]},
               "min_confidence": tau,
+              "min_confidence_by_rounds": {str(r): t for r, t in taus.items()},
               "validation": {"images": "8 held-out training images (640x480)",
-                             "energy_ratio_mean_2_rounds_by_min_confidence": validation}}
-    result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False, tau=tau))
-    result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True, tau=tau)
+                             "energy_ratio_mean_by_rounds_and_min_confidence": validation}}
+    result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False, taus=taus))
+    result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True, taus=taus)
     return result
 
 
 C5_CONFIDENCES = (0.0, 0.5, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85)
 
 
-def c5_pick_confidence(slic, torch, dev, net, first: int, n_val: int):
-    """The decode's minimum confidence with the lowest mean energy ratio
-    (2 warm rounds against plain 10 rounds) on training-distribution images
-    the net never saw (training images first .. first + n_val - 1)."""
+def c5_pick_confidence(slic, torch, dev, net, first: int, n_val: int, rounds=(2,)):
+    """Per warm round count, the decode's minimum confidence with the lowest
+    mean energy ratio (against plain 10 rounds) on training-distribution
+    images the net never saw (training images first .. first + n_val - 1).
+    Returns ({rounds: tau}, {rounds: {tau: ratio}})."""
     import synth
     from synth.configs import warm_train_workload
     S = net.S
@@ -284,22 +287,24 @@ def c5_pick_confidence(slic, torch, dev, net, first: int, n_val: int):
     params = [slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb) for w in vals]
     plain = [float(slic.segment(r, p, 10, want_energy=True)["energy"].cpu()[0])
              for r, p in zip(imgs, params)]
-    table = {}
+    table = {str(n): {} for n in rounds}
     for tau in C5_CONFIDENCES:
         prepared = slic.warm.prepare(net.params, S, tau)
-        ratios = [float(slic.warm.warm_segment(r, p, prepared, 2)["energy"].cpu()[0]) / e
-                  for r, p, e in zip(imgs, params, plain)]
-        table[str(tau)] = round(sum(ratios) / len(ratios), 4)
-    best = min(C5_CONFIDENCES, key=lambda t: table[str(t)])
+        for n in rounds:
+            ratios = [float(slic.warm.warm_segment(r, p, prepared, n)["energy"].cpu()[0]) / e
+                      for r, p, e in zip(imgs, params, plain)]
+            table[str(n)][str(tau)] = round(sum(ratios) / len(ratios), 4)
+    best = {n: min(C5_CONFIDENCES, key=lambda t: table[str(n)][str(t)]) for n in rounds}
     return best, table
 
 
-def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, tau: float):
+def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, taus: dict):
     """The trained net against plain SLIC on ``n_eval`` evaluation images of
     640x480 (or 1920x1080 with ``hd``), one image at a time, with the
-    decode's minimum confidence ``tau``; then the warm start at 2..4 rounds
-    beside plain SLIC after as many associations (one round fewer), and the
-    plain argmax decode (every pixel votes) at 2 rounds."""
+    decode's minimum confidence ``taus[rounds]``; then the warm start at 2..4
+    rounds beside plain SLIC after as many associations (one round fewer)
+    and after as many rounds, and the plain argmax decode (every pixel
+    votes) at 2 rounds."""
     import numpy as np
 
     import synth
@@ -325,6 +330,7 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, tau: fl
                               None, e_plain[i:].data_ptr() if with_energy else None, None, stream,
                               ws_plain.data_ptr(), ws_plain.numel())
 
+    tau = taus[warm_iters]
     prepared = slic.warm.prepare(net.params, S, tau)
 
     def run_warm(rounds=warm_iters, net_buf=prepared, out=e_warm):
@@ -369,17 +375,21 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, tau: fl
     sweep = {}
     e_tmp = torch.empty(n_eval, dtype=torch.float64, device=dev)
     for rounds in (2, 3, 4):
-        t_r = timed(lambda: run_warm(rounds, prepared, e_tmp))
-        run_warm(rounds, prepared, e_tmp)
+        net_r = slic.warm.prepare(net.params, S, taus[rounds])
+        t_r = timed(lambda: run_warm(rounds, net_r, e_tmp))
+        run_warm(rounds, net_r, e_tmp)
         r_w = e_tmp.cpu().numpy() / ep
         run_plain_n(rounds - 1, e_tmp)
         r_p = e_tmp.cpu().numpy() / ep
         run_plain_n(rounds, e_tmp)
         r_same = e_tmp.cpu().numpy() / ep
         sweep[str(rounds)] = {
+            "min_confidence": taus[rounds],
             "plain_same_rounds_energy_ratio_mean": round(float(r_same.mean()), 4),
             "plain_same_rounds_gate_pass_rate": round(float((r_same <= 1.01).mean()), 4),
             "warm_frames_per_s": round(n_eval / t_r, 1),
+            "warm_frames_per_s_fallback_charged": round(
+                n_eval / (t_r + t_plain * float((r_w > 1.01).sum()) / n_eval), 1),
             "energy_ratio_mean": round(float(r_w.mean()), 4),
             "energy_ratio_max": round(float(r_w.max()), 4),
             "gate_pass_rate": round(float((r_w <= 1.01).mean()), 4),
