@@ -103,6 +103,19 @@ int slic_init(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb, void* 
 int slic_init_from_centres(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
                            const float* d_centres, void* hip_stream, void* d_ws, size_t ws_bytes);
 
+/* A frame started from a given first association (a label map computed
+ * elsewhere, e.g. a predicted one): like slic_init, but d_labels0 (device
+ * int32[height][width], row-major, cluster k = row * ns_c + column of
+ * slic_grid's grid) takes the place of the association with the seeds, so
+ * the first update of slic_iterate moves each centre to the mean of the
+ * pixels given to it; a centre given no pixel keeps its seed (Section 3,
+ * cluster centre initialisation).  Entries outside [0, K) take no part in
+ * that update and stand for the pixel's own grid cell in the context's
+ * labels.  d_labels0 may be reused once the call's work has completed on
+ * the stream.  Same workspace and errors as slic_init. */
+int slic_init_from_labels(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                          const int32_t* d_labels0, void* hip_stream, void* d_ws, size_t ws_bytes);
+
 /* n_iters >= 0 rounds of (update every centre to the mean of its pixels;
  * associate every pixel), the loop body of Section 4's listing.
  * slic_iterate(c, a) followed by slic_iterate(c, b) equals

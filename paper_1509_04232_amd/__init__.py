@@ -18,7 +18,7 @@ from ._abi import (EXPORTED, SLIC_COLOR_RGB, SLIC_COLOR_XYZ, SLIC_DISTANCE_SQUAR
                    slic_destroy, slic_filter_stray, slic_segment_batch,
                    slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
                    slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
-                   slic_init_from_centres,
+                   slic_init_from_centres, slic_init_from_labels,
                    slic_iterate, slic_iterate_converge, slic_segment, slic_set_assign_variant,
                    slic_strerror,
                    slic_timing_enable, slic_timing_read, slic_workspace_bytes,
@@ -86,16 +86,27 @@ def workspace_for(p: Params, device=None) -> torch.Tensor:
 
 class Context:
     """A slic_ctx: slic_init on construction (slic_warm_init when a prepared
-    net, ``warm.prepare``, is given), then iterate / enforce / get."""
+    net, ``warm.prepare``, is given; slic_init_from_centres with centres;
+    slic_init_from_labels with a first association), then iterate / enforce
+    / get."""
 
     def __init__(self, p: Params, rgb: torch.Tensor, stream=None, workspace=None,
-                 net: torch.Tensor | None = None, centres: torch.Tensor | None = None):
+                 net: torch.Tensor | None = None, centres: torch.Tensor | None = None,
+                 labels: torch.Tensor | None = None):
         _check_rgb(rgb, p)
         self.params = p
         self._cp = p.c()
         self.stream = stream
         self._rgb = rgb  # kept alive until the conversion has run
-        if centres is not None:  # video warm start from a previous frame's centres
+        if labels is not None:  # a given first association
+            if labels.dtype != torch.int32 or tuple(labels.shape) != (p.height, p.width) or \
+                    not labels.is_contiguous() or labels.device != rgb.device:
+                raise ValueError("labels must be a contiguous int32 (H, W) tensor on the image's "
+                                 "device")
+            self.ws = workspace if workspace is not None else workspace_for(p, rgb.device)
+            self.ctx = slic_init_from_labels(self._cp, rgb.data_ptr(), labels.data_ptr(),
+                                             _stream(stream), self.ws.data_ptr(), self.ws.numel())
+        elif centres is not None:  # video warm start from a previous frame's centres
             if centres.dtype != torch.float32 or tuple(centres.shape) != (p.n_clusters, 5) or \
                     not centres.is_contiguous():
                 raise ValueError("centres must be a contiguous float32 (K, 5) tensor")

@@ -56,6 +56,8 @@ _SIGS = {
     "slic_init": ([ctypes.POINTER(_P), _PP, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "slic_init_from_centres": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t],
                                ctypes.c_int),
+    "slic_init_from_labels": ([ctypes.POINTER(_P), _PP, _P, _P, _P, _P, ctypes.c_size_t],
+                              ctypes.c_int),
     "slic_iterate": ([_P, _I], ctypes.c_int),
     "slic_iterate_converge": ([_P, _I, ctypes.c_float, _P], ctypes.c_int),
     "slic_enforce_connectivity": ([_P, _P], ctypes.c_int),
@@ -134,6 +136,14 @@ def slic_init_from_centres(p: SlicParams, d_rgb: int, d_centres: int, stream: in
     ctx = _P()
     _check(lib.slic_init_from_centres(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_centres, stream,
                                       d_ws, ws_bytes), "slic_init_from_centres")
+    return int(ctx.value)
+
+
+def slic_init_from_labels(p: SlicParams, d_rgb: int, d_labels0: int, stream: int, d_ws: int,
+                          ws_bytes: int) -> int:
+    ctx = _P()
+    _check(lib.slic_init_from_labels(ctypes.byref(ctx), ctypes.byref(p), d_rgb, d_labels0, stream,
+                                     d_ws, ws_bytes), "slic_init_from_labels")
     return int(ctx.value)
 
 

@@ -525,6 +525,35 @@ int slic_init_from_centres(slic_ctx** out, const slic_params* p, const uint8_t* 
     return SLIC_OK;
 }
 
+int slic_init_from_labels(slic_ctx** out, const slic_params* p, const uint8_t* d_rgb,
+                          const int32_t* d_labels0, void* hip_stream, void* d_ws, size_t ws_bytes) {
+    if (!out || !params_ok(p) || !d_rgb || !d_labels0 || !d_ws || !aligned(d_ws))
+        return SLIC_EINVAL;
+    *out = nullptr;
+    if (ws_bytes < slic_workspace_bytes(p)) return SLIC_EINVAL;
+    int rc = check_buffers(d_rgb, d_ws);
+    if (rc == SLIC_OK) rc = check_device_ptr(d_labels0);
+    if (rc) return rc;
+    slic_ctx* c = new (std::nothrow) slic_ctx;
+    if (!c) return SLIC_ENOMEM;
+    bind(c, p, d_ws, hip_stream);
+    const slic_params& q = c->p;
+    // conversion and seeding (which clears the first accumulators), then the
+    // given labels as association launch 0
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess)
+        e = launch_lab_seed(d_rgb, q.width, q.height, q.pitch, q.channels, c->ws, c->g,
+                            (q.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
+    if (e == hipSuccess) e = launch_import_labels(c->ws, q.width, q.height, c->g, d_labels0, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return SLIC_EHIP;
+    }
+    c->t = 1;
+    *out = c;
+    return SLIC_OK;
+}
+
 int slic_iterate(slic_ctx* c, int32_t n_iters) {
     if (!c || n_iters < 0) return SLIC_EINVAL;
     if (c->state != 0) return SLIC_ESTATE;

@@ -171,6 +171,12 @@ hipError_t launch_connectivity_batch(const CclMap& map, int total_tiles, int tot
 // buffer), `passes` passes.
 hipError_t launch_stray_filter(const Workspace& ws, int32_t w, int32_t h, int32_t* labels,
                                int32_t passes, hipStream_t s);
+// A given first association (after launch_lab_seed): ws.labels from
+// `given` (entries outside [0, K) become the pixel's own grid cell), the
+// valid entries accumulated into the first accumulators, the second
+// cleared, so that association launch 1 starts from them.
+hipError_t launch_import_labels(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                                const int32_t* given, hipStream_t s);
 // Centres float[K][5] from the caller into the workspace (stride kCenStride).
 hipError_t launch_import_centres(const Workspace& ws, const Grid& g, const float* in,
                                  hipStream_t s);
