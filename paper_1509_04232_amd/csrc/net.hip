@@ -555,10 +555,13 @@ constexpr int kFusedA2 = kA2N * 16 * kPS;
 constexpr int kFusedW3 = 9 * 16 * kC;            // third layer's weights
 constexpr int kFusedTab = 2 * (kFW + kFH);       // x / S, x % S, y / S, y % S
 constexpr int kFusedLab = 3 * kFW * kFH;         // the tile's own CIELAB, FP32
-constexpr int kXSlots = (kXW * kXH + 255) / 256; // input pixels per thread
+constexpr int kFT = 256;                         // threads per workgroup
+constexpr int kFWaves = kFT / 64;                 // wavefronts per workgroup
+constexpr int kFPerCU = 512 / kFT;                // resident workgroups per compute unit
+constexpr int kXSlots = (kXW * kXH + kFT - 1) / kFT; // input pixels per thread
 constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2 + kFusedW3) * sizeof(unsigned short) +
                              kFusedTab * sizeof(int) + kFusedLab * sizeof(float);
-static_assert(2 * kFusedLds <= 160 * 1024, "two fused-net workgroups must fit one CU's LDS");
+static_assert(kFPerCU * kFusedLds <= 160 * 1024, "the resident workgroups must fit one CU's LDS");
 
 struct FusedImage {
     const float *L, *A, *B;
@@ -570,7 +573,7 @@ struct FusedImage {
     int tiles_x, n_tiles;
 };
 
-__global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeights wt) {
+__global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, NetWeights wt) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned short* sx = reinterpret_cast<unsigned short*>(smem);
     unsigned short* sa1 = sx + kFusedX;
@@ -583,7 +586,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
     const int S = g.S;
 
     // ---- weights and biases, once per workgroup
-    for (int i = threadIdx.x; i < kFusedW3 / 8; i += 256)
+    for (int i = threadIdx.x; i < kFusedW3 / 8; i += kFT)
         reinterpret_cast<u32x4*>(sw3)[i] = reinterpret_cast<const u32x4*>(wt.W3b)[i];
     // first layer: A[o][k] with k = 4 tap + c for taps 0..7, and tap 8 alone
     bf16x8 w1[2][2], w2[9][2];
@@ -628,7 +631,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         const int px0 = (tile % g.tiles_x) * kFW - 3, py0 = (tile / g.tiles_x) * kFH - 3;
 #pragma unroll
         for (int j = 0; j < kXSlots; ++j) {
-            const int q = threadIdx.x + 256 * j;
+            const int q = threadIdx.x + kFT * j;
             const int gx = px0 + q % kXW, gy = py0 + q / kXW;
             pf[j][0] = pf[j][1] = pf[j][2] = 0.0f;
             if (q < kXW * kXH && gx >= 0 && gy >= 0 && gx < g.w && gy < g.h) {
@@ -651,7 +654,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         // CIELAB in FP32, decode tables; then the next tile's loads
 #pragma unroll
         for (int j = 0; j < kXSlots; ++j) {
-            const int q = threadIdx.x + 256 * j;
+            const int q = threadIdx.x + kFT * j;
             if (q >= kXW * kXH) continue;
             *reinterpret_cast<uint2*>(sx + q * 4) =
                 make_uint2(pack2(pf[j][0] / 100.0f, pf[j][1] / 128.0f), pack2(pf[j][2] / 128.0f, 0.0f));
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         __syncthreads();
 
         // ---- first layer
-        for (int nt = wave; nt < kA1N; nt += 4) {
+        for (int nt = wave; nt < kA1N; nt += kFWaves) {
             const int pr = nt * 16 + row;
             const int p = min(pr, kA1W * kA1H - 1);
             const int r = p / kA1W, c = p % kA1W;
@@ -711,7 +714,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         __syncthreads();
 
         // ---- second layer over the 1-pixel halo, two N-tiles at a time
-        for (int pp = wave; 2 * pp < kA2N; pp += 4) {
+        for (int pp = wave; 2 * pp < kA2N; pp += kFWaves) {
             int pr[2], r[2], c[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -763,7 +766,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
         unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
         int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
-        for (int i = threadIdx.x; i < ncells; i += 256) {
+        for (int i = threadIdx.x; i < ncells; i += kFT) {
             const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
             for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
             const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
@@ -777,12 +780,12 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         __syncthreads();
 
         // ---- third layer, phase bias, argmax, decode, accumulate
-        static_assert(kON % 4 == 0, "output tiles split evenly over four wavefronts");
-        constexpr int kPer = kON / 4;
+        static_assert(kON % kFWaves == 0, "output tiles split evenly over the wavefronts");
+        constexpr int kPer = kON / kFWaves;
         float pb[kPer][4];  // b3 + P of this lane's classes, loaded before the MFMAs
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const int p = (wave + 4 * u) * 16 + row;
+            const int p = (wave + kFWaves * u) * 16 + row;
             const int ph = tab[2 * kFW + kFH + p / kFW] * S + tab[kFW + p % kFW];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -800,7 +803,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 // output pixel p = (wave + 4 u) * 16 + row; rows of 32 hold two N-tiles
-                const int p = (wave + 4 * u) * 16 + row;
+                const int p = (wave + kFWaves * u) * 16 + row;
                 const unsigned short* bp = sa2 + ((p / kFW) * kA2W + p % kFW) * kPS + kq * 8;
                 const bf16x8 b = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const u32x4*>(bp + ((t / 3) * kA2W + t % 3) * kPS));
@@ -809,7 +812,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
         }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const int p = (wave + 4 * u) * 16 + row;
+            const int p = (wave + kFWaves * u) * 16 + row;
             const int r = p / kFW, c = p % kFW;
             const int x = x0 + c, y = y0 + r;
             // this lane's classes 4 kq .. 4 kq + 3: best value, lowest class on ties
@@ -865,7 +868,7 @@ __global__ __launch_bounds__(256, 2) void net_fused_kernel(FusedImage g, NetWeig
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < ncells; i += 256) {
+        for (int i = threadIdx.x; i < ncells; i += kFT) {
             const unsigned long long pk = bins[3 * ncells + i];
             const long long cnt = static_cast<long long>(pk >> 40);
             if (cnt == 0) continue;
@@ -1103,7 +1106,7 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
-    const int grid = n_tiles < 2 * cus ? n_tiles : 2 * cus;
+    const int grid = n_tiles < kFPerCU * cus ? n_tiles : kFPerCU * cus;
     static bool lds_set = false;  // above 64 KiB of dynamic LDS needs the opt-in
     if (!lds_set) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(net_fused_kernel),
@@ -1113,7 +1116,7 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
         lds_set = true;
     }
     KernelTimer t("net_fused", s);
-    net_fused_kernel<<<grid, 256, kFusedLds, s>>>(f, wt);
+    net_fused_kernel<<<grid, kFT, kFusedLds, s>>>(f, wt);
     return hipGetLastError();
 }
 
