@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -1101,19 +1102,22 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
     FusedImage f{ws.L, ws.A, ws.B, w, h, g.S, g.ns_c, g.ns_r,
                  params + kOffB1, params + kOffB2, params + kOffB3, params + kOffP,
                  params + kMaxParams, ws.labels, ws.sums, ws.sums + ring, tiles_x, n_tiles};
-    // persistent workgroups: two per compute unit (their LDS fits twice)
+    // persistent workgroups, kFPerCU per compute unit (their LDS fits that often)
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
     const int grid = n_tiles < kFPerCU * cus ? n_tiles : kFPerCU * cus;
-    static bool lds_set = false;  // above 64 KiB of dynamic LDS needs the opt-in
-    if (!lds_set) {
+    // above 64 KiB of dynamic LDS needs the opt-in, once per device (setting
+    // it twice from racing threads is harmless)
+    static std::atomic<unsigned long long> lds_set{0ull};
+    const unsigned long long bit = dev < 64 ? 1ull << dev : 0ull;
+    if (!bit || !(lds_set.load(std::memory_order_acquire) & bit)) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(net_fused_kernel),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(kFusedLds));
         if (e != hipSuccess) return e;
-        lds_set = true;
+        lds_set.fetch_or(bit, std::memory_order_acq_rel);
     }
     KernelTimer t("net_fused", s);
     net_fused_kernel<<<grid, kFT, kFusedLds, s>>>(f, wt);
