@@ -25,6 +25,7 @@
 // Each workgroup converts a tile plus a two-pixel halo into LDS, stores the
 // tile, and seeds every cell whose middle pixel lies in the tile: the window
 // and the gradient's neighbours stay within two pixels of that pixel.
+#include <atomic>
 #include <cmath>
 
 #include "slic_internal.h"
@@ -151,20 +152,27 @@ __device__ __forceinline__ float norm2(float u, float v, float t) {
     return a;
 }
 
-constexpr int kTW = 64, kTH = 32, kHalo = 2;
-constexpr int kSW = kTW + 2 * kHalo, kSH = kTH + 2 * kHalo;  // staged tile
+constexpr int kTW = 64, kTH = 32, kHalo = 2;  // the tile of batches and large frames
 constexpr int kThreads = 1024;
-constexpr int kSeedsPerPass = kThreads / 9;
+// Small frames: with 64 x 32 tiles a 320 x 240 frame keeps only 40 compute
+// units busy with its cube roots; 32 x 16 tiles spread it over 150.  Used
+// when the large tiles would occupy under half of the units (at 640 x 480,
+// 150 large tiles, the small ones' extra halo and seeding passes cost more).
+constexpr int kSmallTW = 32, kSmallTH = 16, kSmallThreads = 512;
 
 // kBatch: the workgroup's image comes from the tile map (a batch) rather
 // than the kernel argument; separate instantiations, so a single-image
-// launch reads no table and takes no branch on the way in.
-template <bool kBatch>
-__global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single, LabSeedTileMap map,
-                                                            LabTables tab) {
+// launch reads no table and takes no branch on the way in.  TW x TH: the
+// tile (plus a kHalo ring), NT threads.
+template <bool kBatch, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void lab_seed_kernel(LabSeedImage single, LabSeedTileMap map,
+                                                      LabTables tab) {
+    constexpr int kSW = TW + 2 * kHalo, kSH = TH + 2 * kHalo;  // staged tile
+    constexpr int kSeedsPerPass = NT / 9;
+    static_assert(NT >= 256, "the sRGB table is loaded by the first 256 threads");
     __shared__ float lin[256];
     __shared__ float sL[kSW * kSH], sA[kSW * kSH], sB[kSW * kSH];
-    __shared__ float grad[kThreads];
+    __shared__ float grad[NT];
     if (threadIdx.x < 256) lin[threadIdx.x] = tab.lin[threadIdx.x];
     LabSeedImage g;
     int bx, by;
@@ -180,10 +188,10 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single,
         by = blockIdx.y;
     }
     __syncthreads();
-    const int x0 = bx * kTW, y0 = by * kTH;
+    const int x0 = bx * TW, y0 = by * TH;
 
     // ---- convert the tile and its halo
-    for (int i = threadIdx.x; i < kSW * kSH; i += kThreads) {
+    for (int i = threadIdx.x; i < kSW * kSH; i += NT) {
         const int x = x0 - kHalo + i % kSW, y = y0 - kHalo + i / kSW;
         if (x < 0 || y < 0 || x >= g.w || y >= g.h) continue;
         float l, a, b;
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single,
         sL[i] = l;
         sA[i] = a;
         sB[i] = b;
-        if (x >= x0 && x < x0 + kTW && y >= y0 && y < y0 + kTH) {
+        if (x >= x0 && x < x0 + TW && y >= y0 && y < y0 + TH) {
             const size_t pi = static_cast<size_t>(y) * g.w + x;
             g.L[pi] = l;
             g.A[pi] = a;
@@ -215,12 +223,12 @@ __global__ __launch_bounds__(kThreads) void lab_seed_kernel(LabSeedImage single,
         const int lo = c * S, hi = min(lo + S, extent);
         return lo + (hi - lo - 1) / 2;
     };
-    int cx0 = x0 / S, cx1 = min((x0 + kTW - 1) / S, g.ns_c - 1);
+    int cx0 = x0 / S, cx1 = min((x0 + TW - 1) / S, g.ns_c - 1);
     if (middle(cx0, g.w) < x0) ++cx0;
-    if (cx1 >= cx0 && middle(cx1, g.w) >= x0 + kTW) --cx1;
-    int cy0 = y0 / S, cy1 = min((y0 + kTH - 1) / S, g.ns_r - 1);
+    if (cx1 >= cx0 && middle(cx1, g.w) >= x0 + TW) --cx1;
+    int cy0 = y0 / S, cy1 = min((y0 + TH - 1) / S, g.ns_r - 1);
     if (middle(cy0, g.h) < y0) ++cy0;
-    if (cy1 >= cy0 && middle(cy1, g.h) >= y0 + kTH) --cy1;
+    if (cy1 >= cy0 && middle(cy1, g.h) >= y0 + TH) --cy1;
     const int ncx = cx1 - cx0 + 1, ncy = cy1 - cy0 + 1;
     if (ncx <= 0 || ncy <= 0) return;  // uniform across the workgroup
     const int nseeds = ncx * ncy;
@@ -308,14 +316,34 @@ LabSeedImage lab_seed_image(const uint8_t* rgb, int32_t w, int32_t h, int32_t pi
     return a;
 }
 
+// Compute units of the current device (looked up once per device).
+int compute_units() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cached[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+        c = 256;
+    cached[dev].store(c, std::memory_order_relaxed);
+    return c;
+}
+
 hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch,
                            int32_t channels, const Workspace& ws, const Grid& grid, int perturb,
                            hipStream_t s) {
     const LabSeedImage a = lab_seed_image(rgb, w, h, pitch, channels, ws, grid, perturb);
     const LabSeedTileMap none{nullptr, nullptr, nullptr};
-    dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
     KernelTimer t("lab_seed", s);
-    lab_seed_kernel<false><<<g, kThreads, 0, s>>>(a, none, tables());
+    const int big = ((w + kTW - 1) / kTW) * ((h + kTH - 1) / kTH);
+    if (2 * big < compute_units()) {
+        dim3 g((w + kSmallTW - 1) / kSmallTW, (h + kSmallTH - 1) / kSmallTH);
+        lab_seed_kernel<false, kSmallTW, kSmallTH, kSmallThreads>
+            <<<g, kSmallThreads, 0, s>>>(a, none, tables());
+    } else {
+        dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
+        lab_seed_kernel<false, kTW, kTH, kThreads><<<g, kThreads, 0, s>>>(a, none, tables());
+    }
     return hipGetLastError();
 }
 
@@ -323,7 +351,7 @@ hipError_t launch_lab_seed_batch(const LabSeedTileMap& map, int total_tiles, hip
     if (!map.images) return hipErrorInvalidValue;
     LabSeedImage unused{};
     KernelTimer t("lab_seed", s);
-    lab_seed_kernel<true><<<total_tiles, kThreads, 0, s>>>(unused, map, tables());
+    lab_seed_kernel<true, kTW, kTH, kThreads><<<total_tiles, kThreads, 0, s>>>(unused, map, tables());
     return hipGetLastError();
 }
 
