@@ -154,11 +154,16 @@ __device__ __forceinline__ float norm2(float u, float v, float t) {
 
 constexpr int kTW = 64, kTH = 32, kHalo = 2;  // the tile of batches and large frames
 constexpr int kThreads = 1024;
-// Small frames: with 64 x 32 tiles a 320 x 240 frame keeps only 40 compute
-// units busy with its cube roots; 32 x 16 tiles spread it over 150.  Used
-// when the large tiles would occupy under half of the units (at 640 x 480,
-// 150 large tiles, the small ones' extra halo and seeding passes cost more).
+// Smaller frames: the kernel is bound by its cube roots, so the time is set
+// by the conversions (tile plus halo) of the busiest compute unit.  With
+// 64 x 32 tiles a 320 x 240 frame keeps 40 units busy and a 640 x 480 frame
+// 150; the smallest tile whose count still fits one workgroup per unit
+// spreads the work: 32 x 16 (720 conversions each) or 40 x 30 (1,496; 256
+// tiles at 640 x 480), else 64 x 32 (2,448), whose halo costs least when
+// every unit gets several tiles.  (32 x 16 tiles at 640 x 480, three per
+// unit, were slower than 64 x 32.)
 constexpr int kSmallTW = 32, kSmallTH = 16, kSmallThreads = 512;
+constexpr int kMidTW = 40, kMidTH = 30;
 
 // kBatch: the workgroup's image comes from the tile map (a batch) rather
 // than the kernel argument; separate instantiations, so a single-image
@@ -335,11 +340,15 @@ hipError_t launch_lab_seed(const uint8_t* rgb, int32_t w, int32_t h, int32_t pit
     const LabSeedImage a = lab_seed_image(rgb, w, h, pitch, channels, ws, grid, perturb);
     const LabSeedTileMap none{nullptr, nullptr, nullptr};
     KernelTimer t("lab_seed", s);
-    const int big = ((w + kTW - 1) / kTW) * ((h + kTH - 1) / kTH);
-    if (2 * big < compute_units()) {
+    const int cus = compute_units();
+    auto tiles = [&](int tw, int th) { return ((w + tw - 1) / tw) * ((h + th - 1) / th); };
+    if (tiles(kSmallTW, kSmallTH) <= cus) {
         dim3 g((w + kSmallTW - 1) / kSmallTW, (h + kSmallTH - 1) / kSmallTH);
         lab_seed_kernel<false, kSmallTW, kSmallTH, kSmallThreads>
             <<<g, kSmallThreads, 0, s>>>(a, none, tables());
+    } else if (tiles(kMidTW, kMidTH) <= cus) {
+        dim3 g((w + kMidTW - 1) / kMidTW, (h + kMidTH - 1) / kMidTH);
+        lab_seed_kernel<false, kMidTW, kMidTH, kThreads><<<g, kThreads, 0, s>>>(a, none, tables());
     } else {
         dim3 g((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
         lab_seed_kernel<false, kTW, kTH, kThreads><<<g, kThreads, 0, s>>>(a, none, tables());
