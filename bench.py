@@ -48,7 +48,7 @@ def assign_bytes(n_pixels: int, n_clusters: int) -> int:
 class Frame:
     """Preallocated buffers for repeated slic_segment calls on one image."""
 
-    def __init__(self, slic, wl, device, squared_distance: bool = False):
+    def __init__(self, slic, wl, device, squared_distance: bool = False, tune: bool = False):
         import numpy as np  # noqa: F401
         import torch
 
@@ -65,11 +65,17 @@ class Frame:
         self.nseg = torch.empty(1, dtype=torch.int32, device=device)
         self.stream = torch.cuda.current_stream().cuda_stream
         self.K = self.p.n_clusters
-        # the library's autotuner picks the association launch variant for
-        # this image size and step (recorded process-wide)
-        self.variant, self.tuned_ms_per_iter = slic.slic_autotune(
-            self.cp, self.rgb.data_ptr(), wl.iters, 5, self.stream, self.ws.data_ptr(),
-            self.ws.numel())
+        # the association launch variant: the library's default for this
+        # size and step (it follows the autotuner's picks and, unlike a
+        # timed choice, is the same under a profiler), or with `tune` the
+        # autotuner's pick (recorded process-wide)
+        if tune:
+            self.variant, self.tuned_ms_per_iter = slic.slic_autotune(
+                self.cp, self.rgb.data_ptr(), wl.iters, 5, self.stream, self.ws.data_ptr(),
+                self.ws.numel())
+        else:
+            self.variant = slic.slic_get_assign_variant(wl.width, wl.height, wl.S)
+            self.tuned_ms_per_iter = None
 
     def run(self, iters: int, enforce: bool) -> None:
         self.slic.slic_segment(self.cp, self.rgb.data_ptr(), iters, 1 if enforce else 0,
