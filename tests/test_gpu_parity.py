@@ -7,6 +7,7 @@ import torch
 
 import oracle
 import synth
+from synth.configs import Workload
 
 pytestmark = pytest.mark.gpu
 
@@ -173,6 +174,28 @@ def test_full_gamut_lab(slic):
     want = oracle.rgb_to_lab(img)
     for g, o in zip(got, want):
         assert np.array_equal(g, o)
+
+
+@pytest.mark.parametrize("w,h,S,perturb", [
+    (333, 257, 8, True),    # 32 x 16 conversion tiles, ragged on both sides
+    (613, 397, 7, True),    # 40 x 30 tiles, ragged
+    (640, 480, 16, False),  # 40 x 30 tiles, exact
+    (1500, 900, 12, True),  # 64 x 32 tiles, ragged
+])
+def test_conversion_tile_shapes(slic, w, h, S, perturb):
+    """Every conversion tile shape the library picks by frame size gives the
+    oracle's CIELAB planes and seeds exactly, ragged tiles included."""
+    img = synth.image_for(Workload("tiles", w, h, max(1, w * h // 2000), 10.0, w + h, S))
+    rgb, pitch = _to_dev(img)
+    p = slic.Params(w, h, S=S, m=10.0, perturb=perturb)
+    ctx = slic.Context(p, rgb)
+    got = [t.cpu().numpy() for t in ctx.lab()]
+    cen, _ = ctx.centres()
+    ctx.close()
+    want = oracle.rgb_to_lab(img)
+    for g, o in zip(got, want):
+        assert np.array_equal(g, o)
+    assert np.array_equal(cen.cpu().numpy(), oracle.seed(want, S, perturb))
 
 
 def test_resume_equals_one_run(slic):
