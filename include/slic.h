@@ -178,6 +178,23 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
                  int32_t* d_labels, float* d_centres, double* d_energy, int32_t* d_n_segments,
                  void* hip_stream, void* d_ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * slic_segment without a workspace argument.  The workspace is a
+ * 256-byte-aligned array of SLIC_NOALLOC_MAX_WORKSPACE bytes that the library
+ * holds on each device it runs on until the process ends; the call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Arguments, outputs and results are those of slic_segment, bit for bit.
+ * SLIC_EINVAL when slic_workspace_bytes(p) exceeds SLIC_NOALLOC_MAX_WORKSPACE
+ * (72 MiB: a 1920x1080 frame at any S >= 7).  Every call on one device shares
+ * that device's array and leaves its contents behind (each call initialises
+ * what it reads): calls that overlap on one device, on different streams or
+ * from different threads, race and give wrong results; serialise them. */
+#define SLIC_NOALLOC_MAX_WORKSPACE (72u << 20)
+int slic_segment_noalloc(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters,
+                         int32_t enforce, int32_t* d_labels, float* d_centres, double* d_energy,
+                         int32_t* d_n_segments, void* hip_stream);
+
 void slic_destroy(slic_ctx* ctx);
 const char* slic_strerror(int code);
 

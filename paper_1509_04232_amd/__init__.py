@@ -19,7 +19,8 @@ from ._abi import (EXPORTED, SLIC_COLOR_RGB, SLIC_COLOR_XYZ, SLIC_DISTANCE_SQUAR
                    slic_enforce_connectivity, slic_energy, slic_get_assign_variant,
                    slic_get_centres, slic_get_lab, slic_get_labels, slic_grid, slic_init,
                    slic_init_from_centres, slic_init_from_labels,
-                   slic_iterate, slic_iterate_converge, slic_segment, slic_set_assign_variant,
+                   slic_iterate, slic_iterate_converge, slic_segment, slic_segment_noalloc,
+                   slic_set_assign_variant, SLIC_NOALLOC_MAX_WORKSPACE,
                    slic_strerror,
                    slic_timing_enable, slic_timing_read, slic_workspace_bytes,
                    SlicNetCrop, slic_net_adam, slic_net_forward, slic_net_loss_grad,

@@ -67,6 +67,7 @@ _SIGS = {
     "slic_get_lab": ([_P, _P, _P, _P], ctypes.c_int),
     "slic_energy": ([_P, _P], ctypes.c_int),
     "slic_segment": ([_PP, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "slic_segment_noalloc": ([_PP, _P, _I, _I, _P, _P, _P, _P, _P], ctypes.c_int),
     "slic_destroy": ([_P], None),
     "slic_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "slic_assign_variants": ([], ctypes.c_int32),
@@ -186,6 +187,17 @@ def slic_segment(p: SlicParams, d_rgb: int, n_iters: int, enforce: int, d_labels
                  stream: int, d_ws: int, ws_bytes: int) -> None:
     _check(lib.slic_segment(ctypes.byref(p), d_rgb, n_iters, enforce, d_labels, d_centres,
                             d_energy, d_n_segments, stream, d_ws, ws_bytes), "slic_segment")
+
+
+def slic_segment_noalloc(p: SlicParams, d_rgb: int, n_iters: int, enforce: int, d_labels: int,
+                         d_centres: int | None, d_energy: int | None, d_n_segments: int | None,
+                         stream: int) -> None:
+    _check(lib.slic_segment_noalloc(ctypes.byref(p), d_rgb, n_iters, enforce, d_labels,
+                                    d_centres, d_energy, d_n_segments, stream),
+           "slic_segment_noalloc")
+
+
+SLIC_NOALLOC_MAX_WORKSPACE = 72 << 20
 
 
 def slic_destroy(ctx: int) -> None:

@@ -451,6 +451,64 @@ hipError_t batch_capture(slic_batch* b) {
     return e;
 }
 
+// The whole listing into a workspace that holds at least
+// slic_workspace_bytes(p) bytes (arguments already validated).
+int enqueue_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, int32_t enforce,
+                    int32_t* d_labels, float* d_centres, double* d_energy, int32_t* d_n_segments,
+                    void* hip_stream, void* d_ws) {
+    slic_ctx c;
+    bind(&c, p, d_ws, hip_stream);
+    c.ws.labels = d_labels;  // associate straight into the caller's buffer
+    if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
+    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
+    if (d_energy &&
+        launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
+                                       d_n_segments, c.stream) != hipSuccess)
+        return SLIC_EHIP;
+    return SLIC_OK;
+}
+
+}  // namespace
+}  // namespace slic
+
+// --------------------------------------------- allocation-free workspace
+
+// The workspace of slic_segment_noalloc: one array per device, loaded with
+// the library's code object and held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in); it uses the device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[SLIC_NOALLOC_MAX_WORKSPACE];
+
+namespace slic {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on the current device, looked up once per device
+// with that device current.
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 }  // namespace slic
 
@@ -650,20 +708,23 @@ int slic_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, in
     int rc = check_buffers(d_rgb, d_ws);
     if (rc) return rc;
     if ((rc = check_device_ptr(d_labels)) != 0) return rc;
-    slic_ctx c;
-    bind(&c, p, d_ws, hip_stream);
-    c.ws.labels = d_labels;  // associate straight into the caller's buffer
-    if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
-    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
-    if (d_energy &&
-        launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
-        return SLIC_EHIP;
-    if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
-        return SLIC_EHIP;
-    if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
-                                       d_n_segments, c.stream) != hipSuccess)
-        return SLIC_EHIP;
-    return SLIC_OK;
+    return enqueue_segment(p, d_rgb, n_iters, enforce, d_labels, d_centres, d_energy,
+                           d_n_segments, hip_stream, d_ws);
+}
+
+int slic_segment_noalloc(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters,
+                         int32_t enforce, int32_t* d_labels, float* d_centres, double* d_energy,
+                         int32_t* d_n_segments, void* hip_stream) {
+    if (!params_ok(p) || !d_rgb || !d_labels || n_iters < 0) return SLIC_EINVAL;
+    if (slic_workspace_bytes(p) > static_cast<size_t>(SLIC_NOALLOC_MAX_WORKSPACE))
+        return SLIC_EINVAL;
+    int rc = check_device_ptr(d_rgb);
+    if (rc == SLIC_OK) rc = check_device_ptr(d_labels);
+    if (rc) return rc;
+    void* ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess) return SLIC_EHIP;
+    return enqueue_segment(p, d_rgb, n_iters, enforce, d_labels, d_centres, d_energy,
+                           d_n_segments, hip_stream, ws);
 }
 
 namespace {

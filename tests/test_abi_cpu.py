@@ -138,3 +138,19 @@ def test_assign_variant_table(abi):
     assert abi.slic_get_assign_variant(640, 480, 16) == vec4[0]
     abi.slic_set_assign_variant(640, 480, 16, 0)
     assert abi.slic_get_assign_variant(640, 480, 16) != 0
+
+
+def test_noalloc_limit_matches_header_and_is_checked_on_the_host(abi):
+    text = open(HEADER).read()
+    m = re.search(r"#define SLIC_NOALLOC_MAX_WORKSPACE \((\d+)u << (\d+)\)", text)
+    assert m and (int(m.group(1)) << int(m.group(2))) == abi.SLIC_NOALLOC_MAX_WORKSPACE
+    # 1920x1080 fits at S = 7, not at S = 6; beyond the limit the call
+    # returns SLIC_EINVAL before any device call (no GPU needed)
+    assert abi.slic_workspace_bytes(_p(abi, width=1920, height=1080, S=7)) <= \
+        abi.SLIC_NOALLOC_MAX_WORKSPACE
+    p = _p(abi, width=1920, height=1080, S=6)
+    assert abi.slic_workspace_bytes(p) > abi.SLIC_NOALLOC_MAX_WORKSPACE
+    assert abi.lib.slic_segment_noalloc(ctypes.byref(p), 256, 2, 1, 256, None, None, None,
+                                        None) == abi.SLIC_EINVAL
+    assert abi.lib.slic_segment_noalloc(ctypes.byref(_p(abi, m=-1.0)), 256, 2, 1, 256, None,
+                                        None, None, None) == abi.SLIC_EINVAL
