@@ -20,7 +20,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Flags that make the oracle's FP32 evaluation order the one written in the
 # source: no contraction into FMA, no fast-math reassociation.
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+# OpenMP splits the loops whose iterations are independent (results do not
+# depend on the thread count).
+CFLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+          "-fno-fast-math"]
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +67,7 @@ def _load():
         "orc_connectivity": [_P, _I, _I, _I, _I, _P, _P, _P],
         "orc_lab_tables": [_P, _P],
         "orc_gradient_at": [_P, _P, _P, _I, _I, _I, _I],
+        "orc_threads": [_I],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -102,6 +106,12 @@ def _check(rc: int, what: str) -> None:
 
 def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel loops: n > 0 sets the count, 0 only
+    queries it.  Results do not depend on it."""
+    return int(_load().orc_threads(n))
 
 
 def qshift() -> int:

@@ -17,6 +17,10 @@
  * every layer.  Weights W[tap][out][in], tap = (dy+1)*3 + (dx+1) reading the
  * input at (x+dx, y+dy).
  *
+ * Threads: the convolutions' output rows are split over OpenMP threads when
+ * built with -fopenmp (each output is the same sum in the same order);
+ * gradient sums over pixels stay sequential.
+ *
  * Arithmetic: FP64 throughout.  With bf16 != 0 the values the GPU stores in
  * bfloat16 are rounded to bfloat16 (round to nearest even) at the same
  * points: the input x, the convolution weights, the ReLU outputs a1 and a2.
@@ -69,6 +73,7 @@ typedef struct {
 
 static void conv(const net_t* n, const double* in, int cin, const double* W, const double* b,
                  int cout, int relu, int round_out, double* out) {
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < n->h; y++)
         for (int x = 0; x < n->w; x++) {
             double* o = out + ((size_t)y * n->w + x) * cout;

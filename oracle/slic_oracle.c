@@ -23,11 +23,20 @@
  *
  * Readings where the paper is silent are marked READING and are collected
  * in the design notes of the repository.
+ *
+ * Threads: loops whose iterations are independent (one pixel, one cell)
+ * are split over OpenMP threads when the file is built with -fopenmp; every
+ * value is still computed by the same operations in the same order, and the
+ * centre sums are exact integers, so results do not depend on the thread
+ * count.  Sums in floating point (the energy) stay sequential.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL 1
@@ -39,6 +48,18 @@
 #define ORC_QSHIFT 18
 
 int orc_version(void) { return 1; }
+
+/* Threads used by the parallel loops: n > 0 sets the count, n == 0 only
+ * queries it; 1 without OpenMP. */
+int orc_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 int orc_qshift(void) { return ORC_QSHIFT; }
 
 /* ------------------------------------------------------------------------
@@ -144,6 +165,7 @@ int orc_rgb_to_lab(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, int3
         return ORC_EINVAL;
     float lin[256], nm[9];
     orc_lab_tables(lin, nm);
+#pragma omp parallel for schedule(static)
     for (int32_t y = 0; y < h; y++) {
         for (int32_t x = 0; x < w; x++) {
             const uint8_t* p = rgb + (size_t)y * pitch + (size_t)x * channels;
@@ -183,6 +205,7 @@ int orc_rgb_to_space(const uint8_t* rgb, int32_t w, int32_t h, int32_t pitch, in
         return ORC_EINVAL;
     float lin[256], nm[9];
     orc_lab_tables(lin, nm);
+#pragma omp parallel for schedule(static)
     for (int32_t y = 0; y < h; y++) {
         for (int32_t x = 0; x < w; x++) {
             const uint8_t* p = rgb + (size_t)y * pitch + (size_t)x * channels;
@@ -250,6 +273,7 @@ int orc_seed(const float* L, const float* A, const float* B, int32_t w, int32_t 
              int32_t perturb, float* centres) {
     if (!L || !A || !B || !centres || w < 1 || h < 1 || S < 1) return ORC_EINVAL;
     int32_t ns_c = (w + S - 1) / S, ns_r = (h + S - 1) / S;
+#pragma omp parallel for schedule(static)
     for (int32_t cy = 0; cy < ns_r; cy++) {
         for (int32_t cx = 0; cx < ns_c; cx++) {
             int32_t x0 = cx * S, x1 = x0 + S < w ? x0 + S : w;
@@ -332,6 +356,7 @@ int orc_assign_ex(const float* L, const float* A, const float* B, int32_t w, int
     if (!L || !A || !B || !centres || !labels || w < 1 || h < 1 || S < 1) return ORC_EINVAL;
     int32_t ns_c = (w + S - 1) / S, ns_r = (h + S - 1) / S;
     float wgt = orc_weight(m, S);
+#pragma omp parallel for schedule(static)
     for (int32_t y = 0; y < h; y++) {
         for (int32_t x = 0; x < w; x++) {
             size_t i = (size_t)y * w + x;
@@ -380,33 +405,54 @@ int orc_update_votes(const float* L, const float* A, const float* B, int32_t w, 
                      int32_t* counts) {
     if (!L || !A || !B || !labels || !centres || !counts || w < 1 || h < 1 || K < 1)
         return ORC_EINVAL;
-    int64_t* sums = (int64_t*)calloc((size_t)K * 5, sizeof(int64_t));
+    for (size_t i = 0; i < (size_t)w * h; i++)
+        if (labels[i] < 0 || labels[i] >= K) return ORC_EINVAL;
+    /* sums[k] = (sum qL, sum qa, sum qb, sum x, sum y, count) */
+    int64_t* sums = (int64_t*)calloc((size_t)K * 6, sizeof(int64_t));
     if (!sums) return ORC_ENOMEM;
-    for (int32_t k = 0; k < K; k++) counts[k] = 0;
     const float scale = (float)(1 << ORC_QSHIFT);
-    for (int32_t y = 0; y < h; y++) {
-        for (int32_t x = 0; x < w; x++) {
-            size_t i = (size_t)y * w + x;
-            int32_t k = labels[i];
-            if (k < 0 || k >= K) {
-                free(sums);
-                return ORC_EINVAL;
+    int failed = 0;
+    /* each thread adds its rows into sums of its own, then into the total;
+     * integer additions give the same total in any order */
+#pragma omp parallel
+    {
+        int64_t* part = (int64_t*)calloc((size_t)K * 6, sizeof(int64_t));
+        if (!part) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(static)
+        for (int32_t y = 0; y < h; y++) {
+            if (!part) continue;
+            for (int32_t x = 0; x < w; x++) {
+                size_t i = (size_t)y * w + x;
+                int32_t k = labels[i];
+                if (votes && !votes[i]) continue;
+                int64_t* s = part + 6 * (size_t)k;
+                s[0] += llrintf(L[i] * scale);
+                s[1] += llrintf(A[i] * scale);
+                s[2] += llrintf(B[i] * scale);
+                s[3] += x;
+                s[4] += y;
+                s[5] += 1;
             }
-            if (votes && !votes[i]) continue;
-            int64_t* s = sums + 5 * (size_t)k;
-            s[0] += llrintf(L[i] * scale);
-            s[1] += llrintf(A[i] * scale);
-            s[2] += llrintf(B[i] * scale);
-            s[3] += x;
-            s[4] += y;
-            counts[k] += 1;
+        }
+        if (part) {
+#pragma omp critical
+            for (size_t j = 0; j < (size_t)K * 6; j++) sums[j] += part[j];
+            free(part);
         }
     }
+    if (failed) {
+        free(sums);
+        return ORC_ENOMEM;
+    }
     const double inv = 1.0 / (double)(1 << ORC_QSHIFT);
+    for (int32_t k = 0; k < K; k++) counts[k] = (int32_t)sums[6 * (size_t)k + 5];
     for (int32_t k = 0; k < K; k++) {
         if (counts[k] == 0) continue;
         double n = (double)counts[k];
-        int64_t* s = sums + 5 * (size_t)k;
+        int64_t* s = sums + 6 * (size_t)k;
         float* c = centres + 5 * (size_t)k;
         for (int j = 0; j < 3; j++) {
             double mean = (double)s[j] / n;
