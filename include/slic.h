@@ -68,7 +68,8 @@ typedef struct {
     int32_t S;             /* grid step >= 1, or 0 to derive it from K */
     int32_t K;             /* desired superpixel count, used only when S == 0:
                               S = max(1, floor(sqrt(N/K) + 0.5)) */
-    float m;               /* compactness, finite and >= 0 */
+    float m;               /* compactness, finite and >= 0, with (m/S) times the
+                              image diagonal at most 1e15 (distances stay finite) */
     int32_t flags;         /* SLIC_PERTURB_SEEDS, SLIC_COLOR_XYZ or SLIC_COLOR_RGB,
                               SLIC_DISTANCE_SQUARED, or 0 (a batch shares one distance) */
     int32_t min_segment;   /* connectivity: components smaller than this many pixels
@@ -230,6 +231,8 @@ int slic_autotune(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters, i
  *  - slic_batch_workspace_bytes: device workspace for the batch (every
  *    image's own workspace plus the tile tables); 0 if any params invalid.
  *  - slic_batch_create: validates every image, lays out the workspace,
+ *    waits for the device to finish its pending work (hipDeviceSynchronize,
+ *    so no kernel still running on any stream can touch the workspace),
  *    uploads the tables (synchronous host-to-device copies) and, if
  *    use_graph, captures the whole pipeline into a HIP graph.  `variant` is
  *    an association variant every image supports, or 0 for the largest such
@@ -336,7 +339,10 @@ int slic_net_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, 
  * of a warm start (0: every pixel; above 1: none, so the first update
  * keeps the seeds); every pixel still carries its decoded label.  Prepare
  * once per parameter set, then run any number of frames with the same step
- * S.  SLIC_EINVAL for S outside 1..32, a negative, NaN or infinite
+ * S: the library records the S each buffer was prepared for (per device and
+ * address), and the warm-start calls reject a buffer prepared for another S,
+ * or not filled by slic_net_prepare on that device, with SLIC_EINVAL.
+ * SLIC_EINVAL for S outside 1..32, a negative, NaN or infinite
  * min_confidence, or a missing or misaligned buffer. */
 size_t slic_net_prepared_bytes(void);
 int slic_net_prepare(int32_t S, const float* d_params, float min_confidence, void* d_net,

@@ -130,6 +130,15 @@ bool params_ok(const slic_params* p) {
     if (static_cast<int64_t>(p->pitch) < static_cast<int64_t>(p->width) * p->channels) return false;
     if (p->S < 0 || (p->S == 0 && p->K < 1)) return false;
     if (!std::isfinite(p->m) || p->m < 0.0f) return false;
+    // (m / S) d_xy, and its square, stay finite for every pixel and centre
+    // of the image (d_xy below the diagonal plus one cell)
+    {
+        Grid g;
+        compute_grid(p, &g);
+        const double diag = std::sqrt(static_cast<double>(p->width) * p->width +
+                                      static_cast<double>(p->height) * p->height) + 2.0 * g.S;
+        if (static_cast<double>(p->m) / g.S * diag > 1e15) return false;
+    }
     if (p->flags & ~(SLIC_PERTURB_SEEDS | SLIC_COLOR_XYZ | SLIC_COLOR_RGB | SLIC_DISTANCE_SQUARED))
         return false;
     if ((p->flags & SLIC_COLOR_XYZ) && (p->flags & SLIC_COLOR_RGB)) return false;
@@ -750,8 +759,11 @@ int check_warm_args(const slic_params* p, const uint8_t* d_rgb, const void* d_ne
     if (!warm_supported(g.S) || g.space != 0 || g.dist != 0 || ws_bytes < slic_workspace_bytes(p))
         return SLIC_EINVAL;
     int rc = check_buffers(d_rgb, d_ws);
+    if (rc == SLIC_OK) rc = check_device_ptr(d_net);
     if (rc) return rc;
-    return check_device_ptr(d_net);
+    // the phase bias is indexed with the image's S: the net must have been
+    // prepared for that S
+    return prepared_step(d_net) == g.S ? SLIC_OK : SLIC_EINVAL;
 }
 
 }  // namespace
@@ -956,7 +968,11 @@ int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_
         for (int v = assign_variant_count(); v >= 1 && variant == 0; --v)
             if (batch_variant_ok(b, v)) variant = v;
     }
-    hipError_t e = batch_upload_lab(b);
+    // the tables are written with synchronous copies: first let every kernel
+    // still pending on the device (on any stream, e.g. the last user of this
+    // memory) finish
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = batch_upload_lab(b);
     if (e == hipSuccess) e = batch_upload_assign(b, variant);
     if (e == hipSuccess) e = batch_upload_ccl(b);
     if (e == hipSuccess && b->use_graph) e = batch_capture(b);
@@ -990,7 +1006,7 @@ int slic_batch_autotune(slic_batch* b, void* hip_stream, int32_t reps, int32_t* 
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SLIC_EHIP;
     int best = 0;
     float best_t = 0.0f;
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = hipDeviceSynchronize();  // the tables are rewritten synchronously
     for (int v = 1; e == hipSuccess && v <= assign_variant_count(); ++v) {
         if (!batch_variant_ok(b, v)) continue;
         e = batch_upload_assign(b, v);

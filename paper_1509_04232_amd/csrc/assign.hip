@@ -74,15 +74,18 @@ __device__ __forceinline__ float eq1_fast(float cl, float ca, float cb, float cx
 }
 
 // Reference argmin over the nine candidates of one pixel (near ties only):
-// kept out of line so the unrolled fast path stays small.
-__device__ __noinline__ int reference_slot(const float4* cen4, const float* ceny, int base,
-                                           int ncx, float l, float a, float b, float xf,
-                                           float yf, float wgt) {
+// kept out of line so the unrolled fast path stays small.  Cells outside the
+// grid are not candidates (the pixel's own cell always is), whatever the
+// other distances are.
+__device__ __noinline__ int reference_slot(const float4* cen4, const float* ceny,
+                                           const int* kidx, int base, int ncx, float l, float a,
+                                           float b, float xf, float yf, float wgt) {
     float bref = 0.0f;
     int sref = -1;
 #pragma unroll 1
     for (int c = 0; c < 9; ++c) {
         const int li = base + (c / 3) * ncx + (c % 3);
+        if (kidx[li] < 0) continue;
         const float4 q = cen4[li];
         const float d = eq1_reference(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, wgt);
         if (sref < 0 || d < bref) {
@@ -385,8 +388,11 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
             }
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                const int slot = static_cast<int>(bk[v] & 15ull);
-                cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
+                // an out-of-grid cell (infinite distance) can only come first
+                // when no distance is finite; the own cell is then taken
+                int slot = static_cast<int>(bk[v] & 15ull);
+                const int cell = base + (slot / 3) * ncx + (slot % 3);
+                cellv[r][v] = kidx[cell] < 0 ? base + ncx + 1 : cell;
             }
             continue;
         }
@@ -415,8 +421,8 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
             const float bf = __uint_as_float(best[v] & ~15u);
             const float sf = __uint_as_float(second[v] & ~15u);
             if (!(bf < __builtin_fmaf(sf, -kCertify, sf)))
-                slot = reference_slot(cen4, ceny, base, ncx, pl[r][v], pa[r][v], pb[r][v],
-                                      static_cast<float>(x + v), yf, g.wgt);
+                slot = reference_slot(cen4, ceny, kidx, base, ncx, pl[r][v], pa[r][v],
+                                      pb[r][v], static_cast<float>(x + v), yf, g.wgt);
             cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
         }
     }

@@ -30,6 +30,9 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "slic_internal.h"
 
@@ -1126,6 +1129,27 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
 
 bool warm_supported(int32_t S) { return S >= 1 && S <= kMaxS; }
 
+// The step S each prepared buffer was filled for, per (device, address).
+namespace {
+std::mutex g_prepared_mu;
+std::map<std::pair<int, uintptr_t>, int32_t> g_prepared;
+}  // namespace
+
+void record_prepared(const void* d_net, int32_t S) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(g_prepared_mu);
+    g_prepared[std::make_pair(dev, reinterpret_cast<uintptr_t>(d_net))] = S;
+}
+
+int32_t prepared_step(const void* d_net) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(g_prepared_mu);
+    auto it = g_prepared.find(std::make_pair(dev, reinterpret_cast<uintptr_t>(d_net)));
+    return it == g_prepared.end() ? 0 : it->second;
+}
+
 }  // namespace slic
 
 using namespace slic;
@@ -1148,7 +1172,9 @@ int slic_net_prepare(int32_t S, const float* d_params, float min_confidence, voi
     const int n = count > 9 * kC * kC ? count : 9 * kC * kC;
     prepare_kernel<<<(n + 255) / 256, 256, 0, s>>>(d_params, wt, count, params,
                                                    params + kMaxParams, min_confidence);
-    return hipGetLastError() == hipSuccess ? SLIC_OK : SLIC_EHIP;
+    if (hipGetLastError() != hipSuccess) return SLIC_EHIP;
+    record_prepared(d_net, S);
+    return SLIC_OK;
 }
 
 int32_t slic_net_param_count(int32_t S) {

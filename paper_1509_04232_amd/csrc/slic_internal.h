@@ -189,6 +189,11 @@ hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out,
 // the first accumulator buffer (as association launch 0 would) and clears
 // the second, so that association launch 1 starts from the net's labels.
 bool warm_supported(int32_t S);
+// slic_net_prepare records the step S each prepared buffer holds (per
+// device and address); prepared_step returns it, 0 for a buffer it never
+// prepared on the current device.
+void record_prepared(const void* d_net, int32_t S);
+int32_t prepared_step(const void* d_net);
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                              const void* d_net, hipStream_t s);
 

@@ -50,7 +50,8 @@ def test_grid_matches_oracle_reading(abi, w, h, S, K):
 
 @pytest.mark.parametrize("bad", [dict(width=0), dict(height=-1), dict(channels=2),
                                  dict(pitch=10), dict(S=-1), dict(S=0, K=0), dict(m=-1.0),
-                                 dict(m=float("nan")), dict(m=float("inf")), dict(flags=16), dict(flags=6),
+                                 dict(m=float("nan")), dict(m=float("inf")), dict(m=1e30), dict(m=2e13),
+                                 dict(flags=16), dict(flags=6),
                                  dict(min_segment=-1), dict(width=1 << 25, height=1),
                                  dict(width=40000, height=40000)])
 def test_invalid_params_rejected(abi, bad):
@@ -154,3 +155,13 @@ def test_noalloc_limit_matches_header_and_is_checked_on_the_host(abi):
                                         None) == abi.SLIC_EINVAL
     assert abi.lib.slic_segment_noalloc(ctypes.byref(_p(abi, m=-1.0)), 256, 2, 1, 256, None,
                                         None, None, None) == abi.SLIC_EINVAL
+
+
+def test_compactness_bound(abi):
+    """(m/S) times the diagonal (plus two cells) may reach 1e15, no more:
+    every distance of Eq. 1 and of its squared form stays finite in FP32."""
+    diag = (640 ** 2 + 480 ** 2) ** 0.5 + 32
+    size = lambda **kw: abi.lib.slic_workspace_bytes(ctypes.byref(_p(abi, **kw)))  # noqa: E731
+    assert size(m=float(1e15 * 16 / diag * 0.999)) > 0
+    assert size(m=float(1e15 * 16 / diag * 1.001)) == 0
+    assert size(m=0.0) > 0

@@ -70,18 +70,30 @@ def test_batch_equals_single_calls(slic, use_graph, enforce):
 
 
 def test_batch_of_the_c4_images_matches_the_oracle(slic):
-    wls = synth.batch_workload()[:6]
+    """All 64 images of the c4 batch (46 Mpix, sizes 320x240 to 1920x1080,
+    S of 8, 16 and 32), through one HIP graph with the autotuned variant, as
+    the benchmark runs them (no connectivity) and with connectivity: every
+    image's labels and segment count equal the oracle's."""
+    wls = synth.batch_workload()
+    assert len(wls) == 64
     imgs = [synth.image_for(w) for w in wls]
+    devs = [_device(i) for i in imgs]
     params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb) for w in wls]
-    b = slic.Batch(params, [_device(i) for i in imgs], wls[0].iters, enforce=True,
-                   use_graph=True)
-    b.run()
+    iters = wls[0].iters
+    plain = slic.Batch(params, devs, iters, use_graph=True)
+    variant, _ = plain.autotune(reps=1)
+    plain.run()
+    merged = slic.Batch(params, devs, iters, enforce=True, variant=variant, use_graph=True)
+    merged.run()
     torch.cuda.synchronize()
-    for wl, img, lab, n in zip(wls, imgs, b.labels, b.n_segments.cpu().numpy()):
+    print(f"c4: 64 images, variant {variant}", flush=True)
+    for j, (wl, img) in enumerate(zip(wls, imgs)):
         want = oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, True)
-        assert np.array_equal(lab.cpu().numpy(), want["seg_labels"]), wl.name
-        assert n == want["n_segments"]
-    b.close()
+        assert np.array_equal(plain.labels[j].cpu().numpy(), want["labels"]), wl.name
+        assert np.array_equal(merged.labels[j].cpu().numpy(), want["seg_labels"]), wl.name
+        assert int(merged.n_segments[j].cpu()) == want["n_segments"], wl.name
+    plain.close()
+    merged.close()
 
 
 def test_batch_autotune_keeps_results(slic):

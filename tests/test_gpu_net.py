@@ -345,3 +345,27 @@ def test_net_rejects_bad_arguments(slic):
     for bad in (-0.1, float("nan"), float("inf")):  # minimum confidence
         with pytest.raises(_abi.SlicError):
             slic.warm.prepare(net.params, 8, bad, out=buf)
+
+
+def test_prepared_net_is_bound_to_its_step(slic):
+    """A net prepared for one S is rejected for a frame of another S (its
+    phase bias is indexed with the frame's S), and a buffer that
+    slic_net_prepare never filled is rejected too; re-preparing the same
+    buffer for the frame's S makes it valid."""
+    from paper_1509_04232_amd import _abi
+    img, _ = _image(96, 64, 72)
+    rgb = _dev(img.reshape(-1))
+    net16 = slic.warm.prepare(_dev(_random_params(16, 73)), 16)
+    prm8 = slic.Params(96, 64, S=8, m=10.0)
+    with pytest.raises(_abi.SlicError) as e:
+        slic.warm.warm_segment(rgb, prm8, net16, 1)
+    assert e.value.code == _abi.SLIC_EINVAL
+    with pytest.raises(_abi.SlicError):
+        slic.Context(prm8, rgb, net=net16)
+    never = torch.zeros(_abi.slic_net_prepared_bytes(), dtype=torch.uint8, device="cuda")
+    with pytest.raises(_abi.SlicError):
+        slic.warm.warm_segment(rgb, prm8, never, 1)
+    slic.warm.prepare(_dev(_random_params(8, 74)), 8, out=net16)
+    out = slic.warm.warm_segment(rgb, prm8, net16, 1)
+    torch.cuda.synchronize()
+    assert int(out["labels"].min()) >= 0
