@@ -16,7 +16,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "slic_oracle.c"), os.path.join(_HERE, "net_oracle.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SLIC_ORACLE_LIB names another build of the same sources (the sanitizer
+# test loads one built with AddressSanitizer and UBSan this way).
+_LIB = os.environ.get("SLIC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+SOURCES = list(_SRCS)
 
 # Flags that make the oracle's FP32 evaluation order the one written in the
 # source: no contraction into FMA, no fast-math reassociation.

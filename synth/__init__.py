@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "synth.c")
-_LIB = os.path.join(_HERE, "libsynth.so")
+# SLIC_SYNTH_LIB names another build of synth.c (see the sanitizer test).
+_LIB = os.environ.get("SLIC_SYNTH_LIB") or os.path.join(_HERE, "libsynth.so")
+SOURCE = _SRC
 
 
 def build(force: bool = True) -> str:
