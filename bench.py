@@ -8,11 +8,14 @@ resident in HBM.  Prints ONE JSON line (rank 0, one GPU):
 
   value       frames/s of the headline workload (c2: 640x480, S=16, m=10,
               10 iterations, perturbed seeds, connectivity)
-  roofline    the dominant kernel (the fused association + accumulation):
-              algorithmic bytes per launch / its average launch duration,
-              measured with HIP events on the launch stream around 200
-              back-to-back launches
-  cpu_baseline the CPU oracle (single thread) on a bounded sample of frames
+  roofline    the dominant kernel (the fused association + accumulation),
+              bound by its vector arithmetic: algorithmic FP32 operations per
+              launch / its average duration inside frames ((frame with 10
+              rounds - frame with 0 rounds) / 10, HIP events on the launch
+              stream) against the non-packed FP32 peak; with its HBM fraction
+              and its VALU instruction rate (committed counters)
+  cpu_baseline the CPU oracle on a bounded sample of frames, on every OpenMP
+              thread (and on one)
   extra       Mpix/s per iteration at 640x480 and 1920x1080, per-kernel
               times (events around each launch, so each includes about 2-3 us
               of event overhead), the 1080p frame rate, the 64-image batch
@@ -33,6 +36,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# FP32 vector peak without packed instructions (the library is built without
+# them): 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane
+# instructions per second, x 2 for a fused multiply-add = 78.6 T ops/s
+VALU_ISSUE_PEAK_T = 39.32
+ALU_PEAK_TFLOPS = 78.64
+# algorithmic FP32 operations per pixel of one association launch: Eq. 1 for
+# each of 9 candidates (3 colour and 2 position differences, 5 squares, 3
+# additions, 2 square roots, the product with m/S and the final sum: 17),
+# 8 comparisons for the argmin, and 5 additions into the centre sums
+ASSIGN_OPS_PER_PIXEL = 9 * 17 + 8 + 5
+VALU_FILE = os.path.join(ROOT, "profiles", "assign_valu_counters.json")
 METRIC = "frames/s & Mpix/s/iter at 640x480 and 1080p; learned vs plain at equal energy"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_c2_traffic.json")
 ASSIGN_SRC = os.path.join(ROOT, "paper_1509_04232_amd", "csrc", "assign.hip")
@@ -96,30 +110,53 @@ def time_frames(torch, frame: Frame, steps: int, warmup: int, iters: int, enforc
     return (time.perf_counter() - t0) / steps
 
 
-KERNELS = ("lab_seed", "assign", "ccl_", "energy")
+def event_frames_ms(torch, frame: Frame, steps: int, iters: int, enforce: bool) -> float:
+    """Milliseconds per frame between two HIP events recorded on the launch
+    stream around `steps` back-to-back frames."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    frame.run(iters, enforce)
+    start.record()
+    for _ in range(steps):
+        frame.run(iters, enforce)
+    stop.record()
+    stop.synchronize()
+    return start.elapsed_time(stop) / steps
 
 
-def assign_launch_ms(slic, torch, frame: Frame, n: int = 200, reps: int = 5) -> float:
-    """Average duration (ms) of one association launch: `n` back-to-back
-    launches (slic_iterate enqueues exactly one per iteration, in the variant
-    the frame uses) between two HIP events recorded on the launch stream,
-    median of `reps` repetitions."""
-    ctx = slic.Context(frame.p, frame.rgb, workspace=frame.ws)
-    try:
-        ctx.iterate(10)
-        start = torch.cuda.Event(enable_timing=True)
-        stop = torch.cuda.Event(enable_timing=True)
-        runs = []
-        for _ in range(reps):
-            start.record()
-            ctx.iterate(n)
-            stop.record()
-            stop.synchronize()
-            runs.append(start.elapsed_time(stop) / n)
-    finally:
-        ctx.close()
+def assign_from_frames_ms(torch, frame: Frame, steps: int, reps: int = 5) -> float:
+    """Average duration (ms) of one association launch inside frames: each
+    round of a frame is one association launch, so (frame with 10 rounds -
+    frame with 0 rounds) / 10, both timed with HIP events on the launch
+    stream (no connectivity); median of `reps` repetitions."""
+    runs = []
+    for _ in range(reps):
+        t10 = event_frames_ms(torch, frame, steps, 10, False)
+        t0 = event_frames_ms(torch, frame, steps, 0, False)
+        runs.append((t10 - t0) / 10)
     runs.sort()
     return runs[len(runs) // 2]
+
+
+def time_frames_with_upload(torch, frame: Frame, steps: int, warmup: int) -> float:
+    """Seconds per frame when every frame is first copied from pinned host
+    memory to the device on the launch stream (the listing of Section 4
+    uploads each frame inside its timed segmentation)."""
+    host = frame.rgb.cpu().pin_memory()
+    wl = frame.wl
+    for _ in range(warmup):
+        frame.rgb.copy_(host, non_blocking=True)
+        frame.run(wl.iters, wl.connectivity)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        frame.rgb.copy_(host, non_blocking=True)
+        frame.run(wl.iters, wl.connectivity)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+KERNELS = ("lab_seed", "assign", "ccl_", "energy")
 
 
 def kernel_times(slic, torch, frame: Frame, steps: int, iters: int, enforce: bool):
@@ -559,23 +596,64 @@ def traffic_from_profile():
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(wl, seconds: float):
+    """The oracle (built -O3, its independent loops split over OpenMP
+    threads; results identical for any thread count) on whole frames of the
+    workload: one thread, then every thread OpenMP is given, each for about
+    `seconds`."""
     import oracle
     import synth
     img = synth.image_for(wl)
-    oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, wl.connectivity, wl.min_segment)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
+    all_threads = oracle.threads()
+
+    def rate(threads):
+        oracle.threads(threads)
         oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, wl.connectivity, wl.min_segment)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds:
-            break
-    return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames of {wl.name} ({wl.width}x{wl.height}, {wl.iters} iterations, "
-                      f"connectivity), single-threaded oracle on {platform.processor() or 'host'}"
-                      f" ({os.cpu_count()} logical CPUs visible)"}
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.segment(img, wl.S, wl.m, wl.iters, wl.perturb, wl.connectivity,
+                           wl.min_segment)
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= seconds:
+                return n, dt
+
+    n1, t1 = rate(1)
+    nn, tn = rate(all_threads)
+    oracle.threads(all_threads)
+    return {"value": nn / tn, "unit": "frames/s", "cores": all_threads, "kind": "oracle",
+            "single_thread_value": n1 / t1,
+            "sample": f"{nn} frames of {wl.name} ({wl.width}x{wl.height}, {wl.iters} "
+                      f"iterations, connectivity) on {all_threads} OpenMP threads, and {n1} "
+                      f"frames on one thread; oracle built -O3 -fopenmp; host CPU: "
+                      f"{cpu_model()}, {os.cpu_count()} logical CPUs visible"}
+
+
+def valu_from_profile():
+    """VALU instructions per pixel of the c2 association from the committed
+    counter summary, or None if it is missing or the kernel source changed
+    since the counters were taken."""
+    try:
+        with open(VALU_FILE) as f:
+            v = json.load(f)
+        src = hashlib.sha256(open(ASSIGN_SRC, "rb").read()).hexdigest()
+        if v.get("assign_src_sha256") != src:
+            return None
+        return v
+    except (OSError, ValueError):
+        return None
 
 
 def main() -> int:
@@ -594,8 +672,8 @@ def main() -> int:
                     help="also run a plain device copy of this many bytes (PMC calibration)")
     ap.add_argument("--workload-only", default=None, metavar="NAME",
                     help="profiling mode: run warmup+steps frames of workload NAME (c1, c2, c3, "
-                         "or c5warm: the warm-start path) and the optional copy, print one line "
-                         "per phase, no JSON")
+                         "c4: the 64-image batch, or c5warm: the warm-start path) and the "
+                         "optional copy, print one line per phase, no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the SLIC path has no multi-GPU mode "
@@ -628,6 +706,19 @@ def main() -> int:
         torch.cuda.synchronize()
         print(f"ran {args.warmup + args.steps} warm-start frames of {w.name}", flush=True)
         return 0
+    if args.workload_only == "c4":
+        # the 64-image batch through one HIP graph, the variant the batch
+        # autotuner picks (as in the c4 leg), without connectivity
+        wls = synth.batch_workload()
+        imgs = [torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev) for w in wls]
+        params = [slic.Params(w.width, w.height, S=w.S, m=w.m, perturb=w.perturb) for w in wls]
+        b = slic.Batch(params, imgs, wls[0].iters, use_graph=True)
+        variant, _ = b.autotune(reps=2)
+        for _ in range(args.warmup + args.steps):
+            b.run()
+        torch.cuda.synchronize()
+        print(f"ran {args.warmup + args.steps} batches of c4 (variant {variant})", flush=True)
+        return 0
     if args.workload_only:
         w = synth.WORKLOADS[args.workload_only]
         f = Frame(slic, w, dev)
@@ -650,19 +741,38 @@ def main() -> int:
     value = 1.0 / sec
 
     ktimes = kernel_times(slic, torch, frame, min(args.steps, 200), wl.iters, wl.connectivity)
-    a_ms = assign_launch_ms(slic, torch, frame)
+    a_ms = assign_from_frames_ms(torch, frame, max(args.steps, 20))
     nbytes = assign_bytes(wl.n_pixels, frame.K)
-    achieved = nbytes / (a_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+    gbps = nbytes / (a_ms * 1e-3) / 1e9
+    ops = ASSIGN_OPS_PER_PIXEL * wl.n_pixels
+    tflops = ops / (a_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
                 "traffic": traffic_from_profile(),
                 "kernel": f"assign_kernel (variant {frame.variant}: "
                           f"{'x'.join(map(str, slic.slic_assign_variant_info(frame.variant)[:2]))} "
                           f"pixels per thread)",
-                "bytes_per_launch": nbytes, "avg_launch_us": round(a_ms * 1e3, 3)}
+                "avg_launch_us": round(a_ms * 1e3, 3),
+                "ops_per_pixel": ASSIGN_OPS_PER_PIXEL, "ops_per_launch": ops,
+                "hbm": {"bytes_per_launch": nbytes, "achieved_gbps": round(gbps, 1),
+                        "peak_gbps": HBM_PEAK_GBPS, "frac": round(gbps / HBM_PEAK_GBPS, 4)}}
+    valu = valu_from_profile()
+    if valu:
+        per_px = valu["c2"]["valu_per_pixel"]
+        lane_t = per_px * wl.n_pixels / (a_ms * 1e-3) / 1e12
+        roofline["valu"] = {"instructions_per_pixel": per_px,
+                            "transcendental_per_pixel": valu["c2"]["trans_per_pixel"],
+                            "achieved_t_lane_instr_per_s": round(lane_t, 2),
+                            "peak_t_lane_instr_per_s": VALU_ISSUE_PEAK_T,
+                            "frac": round(lane_t / VALU_ISSUE_PEAK_T, 4),
+                            "counters": os.path.relpath(VALU_FILE, ROOT)}
 
     extra = {"kernels_c2_event_bracketed": {k: {"avg_us": round(v["avg_ms"] * 1e3, 3),
                                 "per_frame": v["launches_per_frame"]} for k, v in ktimes.items()}}
+    up = time_frames_with_upload(torch, frame, args.steps, args.warmup)
+    extra["c2_with_upload"] = {"frames_per_s": round(1.0 / up, 2), "ms_per_frame": round(up * 1e3, 4),
+                               "upload": "921,600-byte frame from pinned host memory, on the "
+                                         "launch stream, inside every timed frame"}
     if not args.no_extra:
         for name in ("c1", "c2", "c3"):
             w = synth.WORKLOADS[name]
@@ -676,7 +786,7 @@ def main() -> int:
             if name != "c2":
                 tf = time_frames(torch, f, steps, 5, w.iters, w.connectivity)
                 entry["frames_per_s"] = round(1.0 / tf, 1)
-                a = assign_launch_ms(slic, torch, f)
+                a = assign_from_frames_ms(torch, f, steps)
                 b = assign_bytes(w.n_pixels, f.K)
                 entry["assign_avg_us"] = round(a * 1e3, 3)
                 entry["assign_variant"] = f.variant
@@ -687,7 +797,7 @@ def main() -> int:
                 fq = Frame(slic, w, dev, squared_distance=True)
                 tq = (time_frames(torch, fq, steps, 5, 10, False) -
                       time_frames(torch, fq, steps, 5, 0, False)) / 10
-                aq = assign_launch_ms(slic, torch, fq)
+                aq = assign_from_frames_ms(torch, fq, steps)
                 entry["squared_distance"] = {
                     "mpix_per_s_per_iter": round(w.n_pixels / tq / 1e6, 1),
                     "us_per_iter": round(tq * 1e6, 3), "assign_avg_us": round(aq * 1e3, 3),
