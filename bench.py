@@ -284,12 +284,26 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     from synth.configs import warm_train_workload
     S, plain_iters = 16, 10
     t0 = time.perf_counter()
-    train = []
-    for j in range(n_train):
-        w = warm_train_workload(j)
-        train.append((torch.from_numpy(synth.image_for(w).reshape(-1)).to(dev),
-                      slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb)))
-    data = slic.warm.TrainingSet(train, plain_iters)
+    data = None
+    # images generated on host threads (the generator releases the
+    # interpreter) in chunks, each chunk's targets computed on the GPU
+    from concurrent.futures import ThreadPoolExecutor
+    chunk = 512
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        for c0 in range(0, n_train, chunk):
+            wls = [warm_train_workload(j) for j in range(c0, min(n_train, c0 + chunk))]
+            imgs = list(pool.map(synth.image_for, wls))
+            part = [(torch.from_numpy(img.reshape(-1)).to(dev),
+                     slic.Params(w.width, w.height, S=S, m=w.m, perturb=w.perturb))
+                    for w, img in zip(wls, imgs)]
+            more = slic.warm.TrainingSet(part, plain_iters)
+            if data is None:
+                data = more
+            else:
+                data.items.extend(more.items)
+            del part
+            print(f"c5: {len(data)} of {n_train} training images ready", file=sys.stderr,
+                  flush=True)
     net = slic.warm.Net(S, 32, 128, 128, seed=1)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
@@ -302,6 +316,9 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
     tau = taus[2]
     result = {"images": n_eval, "S": S,
               "train": {"images": n_train, "steps": train_steps, "crops": "32 x 128x128",
+                        "training_set": "the first %d of the workload's 20,000 training images%s"
+                                        % (n_train, "" if n_train >= 20000 else
+                                           " (a reduced set)"),
                         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
                         "ms_per_step": round(t_train / max(train_steps, 1) * 1e3, 3),
                         "loss": [[s, round(v, 4)] for s, v in log]},
@@ -311,6 +328,23 @@ def bench_c5(slic, torch, dev, train_steps: int, n_train: int, n_eval: int, reps
                              "energy_ratio_mean_by_rounds_and_min_confidence": validation}}
     result.update(c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=False, taus=taus))
     result["1920x1080"] = c5_evaluate(slic, torch, dev, net, n_eval, reps, hd=True, taus=taus)
+    # the learned start against plain 10-round SLIC at the fewest warm rounds
+    # whose gate passes on at least 90% of the images
+    summary = {}
+    for key, ev in (("640x480", result), ("1920x1080", result["1920x1080"])):
+        ok = [int(r) for r, v in ev["rounds"].items() if v["gate_pass_rate"] >= 0.9]
+        if not ok:
+            summary[key] = {"rounds": None, "note": "the gate passes on fewer than 90% of "
+                                                     "the images at 2 to 4 rounds"}
+            continue
+        r = str(min(ok))
+        v = ev["rounds"][r]
+        summary[key] = {"rounds": int(r), "gate_pass_rate": v["gate_pass_rate"],
+                        "warm_frames_per_s_fallback_charged": v["warm_frames_per_s_fallback_charged"],
+                        "plain10_frames_per_s": ev["plain_frames_per_s"],
+                        "speedup": round(v["warm_frames_per_s_fallback_charged"] /
+                                         ev["plain_frames_per_s"], 3)}
+    result["learned_vs_plain10"] = summary
     return result
 
 
@@ -347,7 +381,8 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, taus: d
     decode's minimum confidence ``taus[rounds]``; then the warm start at 2..4
     rounds beside plain SLIC after as many associations (one round fewer)
     and after as many rounds, and the plain argmax decode (every pixel
-    votes) at 2 rounds."""
+    votes) at 2 rounds.  Both paths are timed without the energy (the
+    gate's input, taken in untimed runs)."""
     import numpy as np
 
     import synth
@@ -377,9 +412,12 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, taus: d
     prepared = slic.warm.prepare(net.params, S, tau)
 
     def run_warm(rounds=warm_iters, net_buf=prepared, out=e_warm):
+        # out=None: no energy (the timed runs, like plain SLIC's; the energy
+        # only feeds the gate, an evaluation device, and is taken untimed)
         for i in range(n_eval):
             slic.slic_warm_segment(cps[i], imgs[i].data_ptr(), net_buf.data_ptr(), rounds,
-                                   0, lab_warm[i].data_ptr(), None, out[i:].data_ptr(), None,
+                                   0, lab_warm[i].data_ptr(), None,
+                                   out[i:].data_ptr() if out is not None else None, None,
                                    stream, ws_warm.data_ptr(), ws_warm.numel())
 
     def run_plain_n(rounds, out):
@@ -401,7 +439,7 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, taus: d
         return runs[len(runs) // 2]
 
     t_plain = timed(lambda: run_plain(False))
-    t_warm = timed(run_warm)
+    t_warm = timed(lambda: run_warm(out=None))
     run_plain(True)
     run_warm()
     torch.cuda.synchronize()
@@ -419,7 +457,7 @@ def c5_evaluate(slic, torch, dev, net, n_eval: int, reps: int, hd: bool, taus: d
     e_tmp = torch.empty(n_eval, dtype=torch.float64, device=dev)
     for rounds in (2, 3, 4):
         net_r = slic.warm.prepare(net.params, S, taus[rounds])
-        t_r = timed(lambda: run_warm(rounds, net_r, e_tmp))
+        t_r = timed(lambda: run_warm(rounds, net_r, None))
         run_warm(rounds, net_r, e_tmp)
         r_w = e_tmp.cpu().numpy() / ep
         run_plain_n(rounds - 1, e_tmp)
@@ -664,16 +702,18 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=2000,
+    ap.add_argument("--train-steps", type=int, default=8000,
                     help="Adam steps of the warm-start net in the c5 leg")
-    ap.add_argument("--train-images", type=int, default=128,
-                    help="c5 training images for the warm-start net")
+    ap.add_argument("--train-images", type=int, default=20000,
+                    help="c5 training images for the warm-start net (the workload's 20,000)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (PMC calibration)")
     ap.add_argument("--workload-only", default=None, metavar="NAME",
                     help="profiling mode: run warmup+steps frames of workload NAME (c1, c2, c3, "
                          "c4: the 64-image batch, or c5warm: the warm-start path) and the "
                          "optional copy, print one line per phase, no JSON")
+    ap.add_argument("--c5-only", action="store_true",
+                    help="run only the learned warm-start leg (c5) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the SLIC path has no multi-GPU mode "
@@ -705,6 +745,11 @@ def main() -> int:
             slic.warm.warm_segment(rgb, p, prepared, 2, workspace=ws)
         torch.cuda.synchronize()
         print(f"ran {args.warmup + args.steps} warm-start frames of {w.name}", flush=True)
+        return 0
+    if args.c5_only:
+        res = bench_c5(slic, torch, dev, args.train_steps, args.train_images, 32,
+                       reps=max(3, args.steps // 100))
+        print(json.dumps({"c5": res}), flush=True)
         return 0
     if args.workload_only == "c4":
         # the 64-image batch through one HIP graph, the variant the batch
