@@ -965,8 +965,15 @@ int slic_batch_create(slic_batch** out, const slic_params* per_image, int32_t n_
         return SLIC_EINVAL;
     }
     if (variant == 0) {  // largest tiles every image supports
-        for (int v = assign_variant_count(); v >= 1 && variant == 0; --v)
-            if (batch_variant_ok(b, v)) variant = v;
+        int best_area = 0;
+        for (int v = 1; v <= assign_variant_count(); ++v) {
+            int tw = 0, th = 0;
+            assign_variant_shape(v, nullptr, nullptr, &tw, &th);
+            if (batch_variant_ok(b, v) && tw * th >= best_area) {
+                best_area = tw * th;
+                variant = v;
+            }
+        }
     }
     // the tables are written with synchronous copies: first let every kernel
     // still pending on the device (on any stream, e.g. the last user of this

@@ -12,20 +12,15 @@
 // Certified fast path.  The kernel first evaluates every candidate with fused
 // multiply-adds and the hardware square root.  It tracks the smallest and
 // second smallest value as integer keys: the distance's bit pattern (a
-// non-negative float orders like its bits) with its low bits replaced by the
-// candidate's offset in the staged window (rows of the window are a power of
-// two apart, so the offset is a compile-time constant per candidate and grows
-// with the cluster index), so one integer minimum and one median of three
-// keep both, and the smallest key names the pixel's cell.  Each fast value F
-// is within 11 u of the exact real distance R and each reference value Q
-// within 4 u (u = 2^-24, relative: every term is non-negative), so
-// Q_c > Q_b whenever F_c > F_b (1 + 31 u).  The keys hide up to 2^k - 1 units
-// of the last place (k low bits); a relative step of 31 u is at most 33 such
-// units.  So if the second key's distance bits exceed the best's by more than
-// 2^k - 1 + 34 units, and the second is at least 2^-60 (no underflow in its
-// squares), the reference argmin is the same candidate and no reference value
-// ties with it.  Otherwise (near ties, about one pixel in 10^4 on natural
-// images) the pixel recomputes every candidate with the reference sequence.
+// non-negative float orders like its bits) with the low four bits replaced
+// by the candidate number, so one integer min and one median-of-three keep
+// both, and the smallest key names the candidate (lowest index first).  Each
+// fast value is within 11 u of the exact real distance and each reference
+// value within 4 u (u = 2^-24; relative, all terms are non-negative); the
+// keys drop at most 2^-19 relative.  So if the best key's distance is below
+// the second's by more than 2^-17 of the latter, the reference argmin is the
+// same candidate and no reference value ties with it.  Otherwise (near ties)
+// the pixel recomputes every candidate with the reference sequence.
 //
 // Update, accumulation half: the pixel's colour enters its cluster's sums as
 // the exact integer rint(v * 2^18); x and y are integers.  A thread merges
@@ -48,22 +43,7 @@ namespace slic {
 namespace {
 
 constexpr int kThreads = 256;
-
-// The staged window's rows are RS cells apart (a power of two at least the
-// window's width): candidate c of a pixel (row c / 3, column c % 3 of the
-// 3 x 3 block around its cell) lies at a compile-time offset from the
-// block's top-left cell, and the offsets fit the keys' low kKeyBits bits.
-template <int RS>
-struct Window {
-    static_assert(RS == 16 || RS == 64, "row stride");
-    static constexpr int kKeyBits = (RS == 16 ? 4 : 6) + 2;
-    static constexpr unsigned kLow = (1u << kKeyBits) - 1u;
-    static constexpr int off(int c) { return (c / 3) * RS + c % 3; }
-    // certified when the second key's distance bits lead the best's by more
-    // than this many units of the last place (see the top of the file)
-    static constexpr unsigned kMargin = kLow + 34u;
-};
-constexpr unsigned kKeyFloor = 0x21800000u;  // 2^-60
+constexpr float kCertify = 0x1p-17f;
 
 // Reference Eq. 1 distance: the exact operation sequence of the definition.
 __device__ __forceinline__ float eq1_reference(float cl, float ca, float cb, float cx, float cy,
@@ -91,30 +71,6 @@ __device__ __forceinline__ float eq1_fast(float cl, float ca, float cb, float cx
     const float dx = cx - xf;
     const float t = __builtin_fmaf(dx, dx, dy2);
     return __builtin_fmaf(wgt, __builtin_amdgcn_sqrtf(t), __builtin_amdgcn_sqrtf(s));
-}
-
-// Reference argmin over the nine candidates of one pixel (near ties only):
-// kept out of line so the unrolled fast path stays small.  Returns the
-// window cell of the winner.  Cells outside the grid are not candidates (the
-// pixel's own cell always is), whatever the other distances are.
-template <int RS>
-__device__ __noinline__ int reference_cell(const float4* cen4, const float* ceny,
-                                           const int* kidx, int base, float l, float a, float b,
-                                           float xf, float yf, float wgt) {
-    float bref = 0.0f;
-    int cref = -1;
-#pragma unroll 1
-    for (int c = 0; c < 9; ++c) {
-        const int li = base + (c / 3) * RS + (c % 3);
-        if (kidx[li] < 0) continue;
-        const float4 q = cen4[li];
-        const float d = eq1_reference(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, wgt);
-        if (cref < 0 || d < bref) {
-            bref = d;
-            cref = li;
-        }
-    }
-    return cref;
 }
 
 // Global (device) memory as a named address space: accesses through such
@@ -147,6 +103,40 @@ __device__ __forceinline__ void store_i4(gmem<int32_t>* p, int a, int b, int c, 
     *reinterpret_cast<gmem<vi4>*>(p) = vi4{a, b, c, d};
 }
 
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef int vi2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ vf2 load_f2(gmem<const float>* p) {
+    return *reinterpret_cast<gmem<const vf2>*>(p);
+}
+
+__device__ __forceinline__ void store_i2(gmem<int32_t>* p, int a, int b) {
+    *reinterpret_cast<gmem<vi2>*>(p) = vi2{a, b};
+}
+
+// Reference argmin over the nine candidates of one pixel (near ties only).
+// A cell outside the grid is staged with an infinite colour distance and
+// every distance of a cell inside it is finite (the compactness bound), so
+// the strict test below never selects an outside cell; the pixel's own cell
+// (slot 4) is the starting choice.
+__device__ __forceinline__ int reference_slot(const float4* cen4, const float* ceny, int base,
+                                              int ncx, float l, float a, float b, float xf,
+                                              float yf, float wgt) {
+    float bref = __builtin_huge_valf();
+    int sref = 4;
+#pragma unroll 1
+    for (int c = 0; c < 9; ++c) {
+        const int li = base + (c / 3) * ncx + (c % 3);
+        const float4 q = cen4[li];
+        const float d = eq1_reference(q.x, q.y, q.z, q.w, ceny[li], l, a, b, xf, yf, wgt);
+        if (d < bref) {
+            bref = d;
+            sref = c;
+        }
+    }
+    return sref;
+}
+
 // A workgroup's image: from the kernel argument (one image) or, for a batch,
 // from the image table through the tile-to-image map.
 template <bool kBatch>
@@ -165,37 +155,34 @@ __device__ __forceinline__ void resolve_image(const AssignImage& single, const A
     }
 }
 
-// Shared-memory layout (dynamic): for every slot of the staged window (the
-// workgroup's cells plus a one-cell ring, out-of-grid cells included; rows
-// RS slots apart, slots past a row's last cell unused):
+// Shared-memory layout (dynamic): for every cell of the staged window
+// (the workgroup's cells plus a one-cell ring, out-of-grid cells included):
 //   float4 cen4[n] (L, a, b, x), float ceny[n], int kidx[n] (-1: none),
-//   u64 bins[n][4] (sum qL, sum qa, sum qb, packed x'|y'<<20|count<<40;
-//   x', y' are offsets from the tile's corner), one cell's four together so
-//   that a run's four atomics share one address.
-__host__ __device__ inline size_t assign_lds_bytes(int nslots) {
-    return static_cast<size_t>(nslots) * (16 + 4 + 4 + 32) + 16;
+//   u64 bins[4][n] (sum qL, sum qa, sum qb, packed x'|y'<<20|count<<40).
+__host__ __device__ inline size_t assign_lds_bytes(int ncells) {
+    return static_cast<size_t>(ncells) * (16 + 4 + 4 + 32) + 16;
 }
 
 // Launch shape of a variant: each thread owns VEC horizontally adjacent
-// pixels in each of ROWS consecutive rows.  VEC = 4 uses 16-byte loads and
-// evaluates each staged centre once for the four pixels, so it needs the
-// four pixels in one cell (S % 4 == 0) and aligned rows (width % 4 == 0).
+// pixels in each of ROWS consecutive rows.  VEC = 2 or 4 uses 8- or 16-byte
+// loads and evaluates each staged centre once for the VEC pixels, so it
+// needs them in one cell (S % VEC == 0) and aligned rows (width % VEC == 0).
 template <int VEC, int ROWS>
 struct Shape {
-    static constexpr int kTX = VEC == 1 ? 32 : 16;  // threads per row
+    static constexpr int kTX = VEC == 4 ? 16 : 32;  // threads per row
     static constexpr int kTY = kThreads / kTX;
     static constexpr int kTileW = kTX * VEC;
     static constexpr int kTileH = kTY * ROWS;
     static constexpr int kPx = VEC * ROWS;
 };
 
-__device__ __forceinline__ void add_bin(unsigned long long* bins, int cell, long long rl,
-                                        long long ra, long long rb, unsigned long long rxyc) {
-    unsigned long long* p = bins + 4 * cell;
-    atomicAdd(p, static_cast<unsigned long long>(rl));
-    atomicAdd(p + 1, static_cast<unsigned long long>(ra));
-    atomicAdd(p + 2, static_cast<unsigned long long>(rb));
-    atomicAdd(p + 3, rxyc);
+__device__ __forceinline__ void add_bin(unsigned long long* bins, int ncells, int cell,
+                                        long long rl, long long ra, long long rb,
+                                        unsigned long long rxyc) {
+    atomicAdd(bins + cell, static_cast<unsigned long long>(rl));
+    atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(ra));
+    atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(rb));
+    atomicAdd(bins + 3 * ncells + cell, rxyc);
 }
 
 // The squared-sum distance of the SLIC paper the method builds on (an
@@ -222,11 +209,10 @@ enum AssignMode { kModeSingle = 0, kModeConverge = 1, kModeBatch = 2 };
 
 // The Eq. 1 variants are held to 128 VGPRs (four waves per SIMD), which
 // they need for latency hiding at large frames.
-template <int VEC, int ROWS, int DIST, int MODE, int RS>
+template <int VEC, int ROWS, int DIST, int MODE>
 __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     AssignImage single, AssignTileMap map, long long t, Converge cv) {
     using Sh = Shape<VEC, ROWS>;
-    using W = Window<RS>;
     constexpr bool kConv = MODE == kModeConverge;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_shift;
@@ -265,36 +251,42 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
     const int gx_hi = (min(x0 + Sh::kTileW, g.w) - 1) / S + 1;
     const int gy_hi = (min(y0 + Sh::kTileH, g.h) - 1) / S + 1;
-    const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1;
-    const int nslots = ncy * RS;  // ncx <= RS (checked on the host)
+    const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
     float4* cen4 = reinterpret_cast<float4*>(smem);
-    float* ceny = reinterpret_cast<float*>(cen4 + nslots);
-    int* kidx = reinterpret_cast<int*>(ceny + nslots);
-    // 24 * nslots bytes precede the bins, a multiple of 8; offsets from smem
+    float* ceny = reinterpret_cast<float*>(cen4 + ncells);
+    int* kidx = reinterpret_cast<int*>(ceny + ncells);
+    // 24 * ncells bytes precede the bins, a multiple of 8; offsets from smem
     // keep the bins' LDS address space visible to the compiler, so their
     // atomics are LDS atomics rather than flat ones
     unsigned long long* bins =
-        reinterpret_cast<unsigned long long*>(smem + static_cast<size_t>(nslots) * 24);
+        reinterpret_cast<unsigned long long*>(smem + static_cast<size_t>(ncells) * 24);
 
     // ---- staging of the candidate centres, in two halves: the loads of a
-    // window slot (the centre the previous launch used and, from the second
+    // window cell (the centre the previous launch used and, from the second
     // launch on, the previous launch's sums), then the means, the owner's
-    // stores and the LDS entries
+    // stores and the LDS entries.  The loads are branch-free, from a clamped
+    // cell: a branch around them would make their first use, and hence the
+    // wait for them, come early.
     struct Slot {
         float4 old4;
         float oldy;
         long long sv[kSumStride];
-        int k;  // cluster, -1: past the row's last cell or outside the grid
+        int k;       // cluster, -1: past the window or outside the grid
+        int cx, cy;  // its grid cell
     };
-    // (branch-free, from a clamped slot: a branch around the loads would
-    // make their first use, and hence the wait for them, come early)
     gmem<const long long>* const sums_src = sums_prev ? sums_prev : sums_acc;
+    // row of window cell i: floor((i + 1/2) / ncx) through the hardware
+    // reciprocal; for i < 4096 and ncx <= 64 the product is within 2^-10 of
+    // the quotient, which lies at least 1/128 from an integer, so the floor
+    // is exact
+    const float inv_ncx = __builtin_amdgcn_rcpf(static_cast<float>(ncx));
     auto stage_load = [&](int i) {
         Slot st;
-        const int cxr = i & (RS - 1);
-        const int cx = gx_lo + cxr, cy = gy_lo + i / RS;
-        const bool live = i < nslots && cxr < ncx && cx >= 0 && cy >= 0 && cx < g.ns_c &&
-                          cy < g.ns_r;
+        const int row = static_cast<int>((static_cast<float>(i) + 0.5f) * inv_ncx);
+        const int cx = gx_lo + (i - row * ncx), cy = gy_lo + row;
+        st.cx = cx;
+        st.cy = cy;
+        const bool live = i < ncells && cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
         st.k = live ? cy * g.ns_c + cx : -1;
         const int kk = live ? st.k : 0;
         gmem<float>* c = cen + static_cast<size_t>(kk) * kCenStride;
@@ -305,58 +297,62 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         for (int j = 0; j < kSumStride; ++j) st.sv[j] = sp[j];
         return st;
     };
+    // the previous launch's means (an empty cluster keeps its centre); the
+    // owner stores the new centre and count (and the convergence shift)
+    auto update_centre = [&](const long long* sv, float4 old4, float oldy, bool owner,
+                             gmem<float>* c, int k, float4* vout, float* vyout) {
+        // the means are computed unconditionally (and selected), so the
+        // sums' loads are not deferred behind a test of the count
+        const long long n = sv[5];
+        const double dn = static_cast<double>(n > 0 ? n : 1);
+        const double inv = 1.0 / static_cast<double>(1 << kQShift);
+        const double ml = static_cast<double>(sv[0]) / dn;
+        const double ma = static_cast<double>(sv[1]) / dn;
+        const double mb = static_cast<double>(sv[2]) / dn;
+        const float4 m4 = make_float4(static_cast<float>(ml * inv), static_cast<float>(ma * inv),
+                                      static_cast<float>(mb * inv),
+                                      static_cast<float>(static_cast<double>(sv[3]) / dn));
+        const float my = static_cast<float>(static_cast<double>(sv[4]) / dn);
+        const bool moved = n > 0;
+        const float4 v = make_float4(moved ? m4.x : old4.x, moved ? m4.y : old4.y,
+                                     moved ? m4.z : old4.z, moved ? m4.w : old4.w);
+        const float vy = moved ? my : oldy;
+        if (owner && moved) {
+            if constexpr (kConv) {  // L1 shift, each component rint(|d| 2^18)
+                const double q = static_cast<double>(1 << kQShift);
+                my_shift += llrint(fabs(static_cast<double>(v.x) - old4.x) * q) +
+                            llrint(fabs(static_cast<double>(v.y) - old4.y) * q) +
+                            llrint(fabs(static_cast<double>(v.z) - old4.z) * q) +
+                            llrint(fabs(static_cast<double>(v.w) - old4.w) * q) +
+                            llrint(fabs(static_cast<double>(vy) - oldy) * q);
+            }
+            store_f4(c, v);
+            c[4] = vy;
+        }
+        if (owner) as_global(g.counts)[k] = static_cast<int32_t>(n);
+        *vout = v;
+        *vyout = vy;
+    };
     auto stage_finish = [&](int i, const Slot& st) {
-        if (i >= nslots) return;
-        const int cxr = i & (RS - 1);
-        if (cxr >= ncx) return;  // past the row's last cell
-        for (int j = 0; j < 4; ++j) bins[4 * i + j] = 0ull;
+        if (i >= ncells) return;
+        const int cx = st.cx, cy = st.cy;
+        for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
         if (st.k < 0) {
-            // no centre here: a colour distance of about 1e18, finite (so its
-            // key is an ordinary float) and above every real distance (at
-            // most a few hundred plus (m/S) d_xy <= 1e15), never wins
-            cen4[i] = make_float4(1e18f, 0.0f, 0.0f, 0.0f);
+            // no centre here: an infinite colour distance never wins
+            cen4[i] = make_float4(__builtin_huge_valf(), 0.0f, 0.0f, 0.0f);
             ceny[i] = 0.0f;
             kidx[i] = -1;
             return;
         }
         const int k = st.k;
-        const int cx = gx_lo + cxr, cy = gy_lo + i / RS;
         kidx[i] = k;
         const bool owner = (cx * S) / Sh::kTileW == bx && (cy * S) / Sh::kTileH == by;
         gmem<float>* c = cen + static_cast<size_t>(k) * kCenStride;
-        const float4 old4 = st.old4;
+        const float4 old4 = st.old4;  // the centre the previous launch used
         const float oldy = st.oldy;
         float4 v = old4;
         float vy = oldy;
-        if (sums_prev) {
-            const long long n = st.sv[5];
-            const double dn = static_cast<double>(n > 0 ? n : 1);
-            const double inv = 1.0 / static_cast<double>(1 << kQShift);
-            const double ml = static_cast<double>(st.sv[0]) / dn;
-            const double ma = static_cast<double>(st.sv[1]) / dn;
-            const double mb = static_cast<double>(st.sv[2]) / dn;
-            const float4 m4 = make_float4(static_cast<float>(ml * inv), static_cast<float>(ma * inv),
-                                          static_cast<float>(mb * inv),
-                                          static_cast<float>(static_cast<double>(st.sv[3]) / dn));
-            const float my = static_cast<float>(static_cast<double>(st.sv[4]) / dn);
-            const bool moved = n > 0;  // an empty cluster keeps its centre
-            v = make_float4(moved ? m4.x : old4.x, moved ? m4.y : old4.y, moved ? m4.z : old4.z,
-                            moved ? m4.w : old4.w);
-            vy = moved ? my : oldy;
-            if (owner && moved) {
-                if constexpr (kConv) {  // L1 shift, each component rint(|d| 2^18)
-                    const double q = static_cast<double>(1 << kQShift);
-                    my_shift += llrint(fabs(static_cast<double>(v.x) - old4.x) * q) +
-                                llrint(fabs(static_cast<double>(v.y) - old4.y) * q) +
-                                llrint(fabs(static_cast<double>(v.z) - old4.z) * q) +
-                                llrint(fabs(static_cast<double>(v.w) - old4.w) * q) +
-                                llrint(fabs(static_cast<double>(vy) - oldy) * q);
-                }
-                store_f4(c, v);
-                c[4] = vy;
-            }
-            if (owner) as_global(g.counts)[k] = static_cast<int32_t>(n);
-        }
+        if (sums_prev) update_centre(st.sv, old4, oldy, owner, c, k, &v, &vy);
         if (owner) {
             gmem<long long>* z = sums_next + static_cast<size_t>(k) * kSumStride;
             for (int j = 0; j < kSumStride; ++j) z[j] = 0;
@@ -365,25 +361,34 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         ceny[i] = vy;
     };
 
-    // The thread's first slot is loaded before its pixels: a wave's loads
-    // return in order, so the staging and the barrier after it wait only for
-    // the centres, and the pixel data arrives while other waves compute.
-    const Slot first = stage_load(threadIdx.x);
-    __builtin_amdgcn_sched_barrier(0);  // keep the pixel loads after these
+    // Variants with several rows per thread (large frames, where every
+    // workgroup of a launch is resident at once) load the thread's first cell
+    // before its pixels: a wave's loads return in order, so the staging and
+    // the barrier after it wait only for the centres while the pixel data is
+    // still arriving.  One-row variants (small frames, mostly one wave per
+    // SIMD) load the pixels first and only the cells they hold: there the
+    // loads of the waves without a cell would delay their pixels.
+    constexpr bool kStageFirst = ROWS >= 2;
+    Slot first;
+    first.k = -1;
+    if constexpr (kStageFirst) {
+        first = stage_load(threadIdx.x);
+        __builtin_amdgcn_sched_barrier(0);  // keep the pixel loads after these
+    }
 
     // ---- prefetch this thread's pixels (they do not depend on the centres).
-    // Every lane loads (pixels outside the image read a clamped position;
-    // they are associated but neither stored nor accumulated), so the loads
-    // are issued unconditionally.
+    // Every lane loads (pixels outside the image read a clamped position and
+    // are then zeroed), so the loads are issued unconditionally.
     float pl[ROWS][VEC], pa[ROWS][VEC], pb[ROWS][VEC];
     {
         gmem<const float>* const Lg = as_global(g.L);
         gmem<const float>* const Ag = as_global(g.A);
         gmem<const float>* const Bg = as_global(g.B);
-        const int xc = min(x, g.w - VEC);  // VEC = 4 needs width % 4 == 0
+        const int xc = min(x, g.w - VEC);  // VEC > 1 needs width % VEC == 0
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int y = y0 + ty * ROWS + r;
+            const bool in = col_ok && y < g.h;
             const size_t pi = static_cast<size_t>(min(y, g.h - 1)) * g.w + xc;
             if constexpr (VEC == 4) {
                 const float4 l4 = load_f4(Lg + pi);
@@ -392,42 +397,89 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
                 pl[r][0] = l4.x; pl[r][1] = l4.y; pl[r][2] = l4.z; pl[r][3] = l4.w;
                 pa[r][0] = a4.x; pa[r][1] = a4.y; pa[r][2] = a4.z; pa[r][3] = a4.w;
                 pb[r][0] = b4.x; pb[r][1] = b4.y; pb[r][2] = b4.z; pb[r][3] = b4.w;
+            } else if constexpr (VEC == 2) {
+                const vf2 l2 = load_f2(Lg + pi), a2 = load_f2(Ag + pi), b2 = load_f2(Bg + pi);
+                pl[r][0] = l2.x; pl[r][1] = l2.y;
+                pa[r][0] = a2.x; pa[r][1] = a2.y;
+                pb[r][0] = b2.x; pb[r][1] = b2.y;
             } else {
                 pl[r][0] = Lg[pi];
                 pa[r][0] = Ag[pi];
                 pb[r][0] = Bg[pi];
             }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                pl[r][v] = in ? pl[r][v] : 0.0f;
+                pa[r][v] = in ? pa[r][v] : 0.0f;
+                pb[r][v] = in ? pb[r][v] : 0.0f;
+            }
         }
     }
 
-    stage_finish(threadIdx.x, first);
-    for (int i = threadIdx.x + kThreads; i < nslots; i += kThreads) stage_finish(i, stage_load(i));
+    if constexpr (kStageFirst) {
+        stage_finish(threadIdx.x, first);
+        for (int i = threadIdx.x + kThreads; i < ncells; i += kThreads)
+            stage_finish(i, stage_load(i));
+    } else {
+        // one loop, each cell's loads and means together (the compiler then
+        // overlaps the five FP64 divisions of a cell)
+        for (int i = threadIdx.x; i < ncells; i += kThreads) {
+            const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
+            for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
+            if (cx < 0 || cy < 0 || cx >= g.ns_c || cy >= g.ns_r) {
+                // no centre here: an infinite colour distance never wins
+                cen4[i] = make_float4(__builtin_huge_valf(), 0.0f, 0.0f, 0.0f);
+                ceny[i] = 0.0f;
+                kidx[i] = -1;
+                continue;
+            }
+            const int k = cy * g.ns_c + cx;
+            kidx[i] = k;
+            const bool owner = (cx * S) / Sh::kTileW == bx && (cy * S) / Sh::kTileH == by;
+            gmem<float>* c = cen + static_cast<size_t>(k) * kCenStride;
+            // every load first, so that one memory round trip serves them all
+            const float4 old4 = load_f4(c);  // the centre the previous launch used
+            const float oldy = c[4];
+            long long sv[kSumStride] = {};
+            if (sums_prev) {
+                gmem<const long long>* sp = sums_prev + static_cast<size_t>(k) * kSumStride;
+#pragma unroll
+                for (int j = 0; j < kSumStride; ++j) sv[j] = sp[j];
+            }
+            float4 v = old4;
+            float vy = oldy;
+            if (sums_prev) update_centre(sv, old4, oldy, owner, c, k, &v, &vy);
+            if (owner) {
+                gmem<long long>* z = sums_next + static_cast<size_t>(k) * kSumStride;
+                for (int j = 0; j < kSumStride; ++j) z[j] = 0;
+            }
+            cen4[i] = v;
+            ceny[i] = vy;
+        }
+    }
     __syncthreads();
     if (my_shift) atomicAdd(&s_shift, static_cast<unsigned long long>(my_shift));
 
     // ---- associate: fast distances for every candidate, shared by the VEC
-    // pixels of a row (they lie in one cell).  base: the window slot of the
-    // top-left candidate (columns past the image edge use the tile's first
-    // cell, so every staged-window index stays in range).
-    const int gx_rel = static_cast<int>(static_cast<unsigned>(col_ok ? x : x0) /
-                                        static_cast<unsigned>(S)) - gx_lo - 1;
+    // pixels of a row (they lie in one cell)
+    // window column of the left candidates (columns past the image edge use the
+    // tile's first cell, so every staged-window index stays in range)
+    const int gx_rel = (col_ok ? x / S : x0 / S) - gx_lo - 1;
     int cellv[ROWS][VEC];
+    unsigned need = 0;  // pixels whose fast argmin is not certified: bit r * VEC + v
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int y = y0 + ty * ROWS + r;
         const float yf = static_cast<float>(y);
-        const int cyr = static_cast<int>(static_cast<unsigned>(min(y, g.h - 1)) /
-                                         static_cast<unsigned>(S));
-        const int base = (cyr - gy_lo - 1) * RS + gx_rel;
+        const int base = (min(y, g.h - 1) / S - gy_lo - 1) * ncx + gx_rel;
         if constexpr (DIST == 1) {
-            // exact: (distance bits, offset) as one 64-bit key, lowest offset
-            // (lowest cluster index) on ties
+            // exact: (distance bits, slot) as one 64-bit key, lowest slot on ties
             unsigned long long bk[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) bk[v] = ~0ull;
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                const int li = base + W::off(c);
+                const int li = base + (c / 3) * ncx + (c % 3);
                 const float4 q = cen4[li];
                 const float dy = ceny[li] - yf;
                 const float dy2 = dy * dy;
@@ -436,28 +488,27 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
                     const float d = dist_squared(q.x, q.y, q.z, q.w, dy2, pl[r][v], pa[r][v],
                                                  pb[r][v], static_cast<float>(x + v), g.wgt);
                     const unsigned long long key =
-                        (static_cast<unsigned long long>(__float_as_uint(d)) << W::kKeyBits) |
-                        static_cast<unsigned long long>(W::off(c));
+                        (static_cast<unsigned long long>(__float_as_uint(d)) << 4) |
+                        static_cast<unsigned long long>(c);
                     bk[v] = key < bk[v] ? key : bk[v];
                 }
             }
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                // an out-of-grid cell (huge distance) can only come first when
-                // no distance is finite; the own cell is then taken
-                const int cell = base + static_cast<int>(bk[v] & W::kLow);
-                cellv[r][v] = kidx[cell] < 0 ? base + W::off(4) : cell;
+                // an out-of-grid cell (infinite distance) can only come first
+                // when no distance is finite; the own cell is then taken
+                int slot = static_cast<int>(bk[v] & 15ull);
+                const int cell = base + (slot / 3) * ncx + (slot % 3);
+                cellv[r][v] = kidx[cell] < 0 ? base + ncx + 1 : cell;
             }
             continue;
         }
-        // keys as floats: non-negative, finite, so float order is bit order,
-        // and the median-of-three instruction keeps the best two
-        float best[VEC], second[VEC];
+        unsigned best[VEC], second[VEC];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) best[v] = second[v] = __uint_as_float(0x7F7FFFFFu);
+        for (int v = 0; v < VEC; ++v) best[v] = second[v] = 0xFFFFFFFFu;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-            const int li = base + W::off(c);
+            const int li = base + (c / 3) * ncx + (c % 3);
             const float4 q = cen4[li];
             const float dy = ceny[li] - yf;
             const float dy2 = dy * dy;
@@ -465,43 +516,45 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
             for (int v = 0; v < VEC; ++v) {
                 const float d = eq1_fast(q.x, q.y, q.z, q.w, dy2, pl[r][v], pa[r][v], pb[r][v],
                                          static_cast<float>(x + v), g.wgt);
-                const float key = __uint_as_float((__float_as_uint(d) & ~W::kLow) |
-                                                  static_cast<unsigned>(W::off(c)));
-                // median of (best, second, key) is the new second; the
-                // median of (best, key, 0) the new best
-                second[v] = __builtin_amdgcn_fmed3f(best[v], second[v], key);
-                best[v] = __builtin_amdgcn_fmed3f(best[v], key, 0.0f);
+                const unsigned key = (__float_as_uint(d) & ~15u) | static_cast<unsigned>(c);
+                // median of (best, second, key) given best <= second
+                second[v] = max(best[v], min(second[v], key));
+                best[v] = min(best[v], key);
             }
         }
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const unsigned bb = __float_as_uint(best[v]);
-            const unsigned tb = bb & ~W::kLow, ts = __float_as_uint(second[v]) & ~W::kLow;
-            int cell = base + static_cast<int>(bb & W::kLow);
-            if (!(ts - tb > W::kMargin && ts >= kKeyFloor))
-                cell = reference_cell<RS>(cen4, ceny, kidx, base, pl[r][v], pa[r][v], pb[r][v],
-                                          static_cast<float>(x + v), yf, g.wgt);
-            cellv[r][v] = cell;
+            const int slot = static_cast<int>(best[v] & 15u);
+            const float bf = __uint_as_float(best[v] & ~15u);
+            const float sf = __uint_as_float(second[v] & ~15u);
+            if (!(bf < __builtin_fmaf(sf, -kCertify, sf))) need |= 1u << (r * VEC + v);
+            cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
+        }
+    }
+    // near ties (a few pixels per frame): the reference argmin, after the
+    // fast pass, whose keys are then dead, and inline (a call would pin the
+    // fast pass's live values to the callee-saved registers)
+    if (need) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = y0 + ty * ROWS + r;
+            const int base = (min(y, g.h - 1) / S - gy_lo - 1) * ncx + gx_rel;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                if (!(need & (1u << (r * VEC + v)))) continue;
+                const int slot = reference_slot(cen4, ceny, base, ncx, pl[r][v], pa[r][v],
+                                                pb[r][v], static_cast<float>(x + v),
+                                                static_cast<float>(y), g.wgt);
+                cellv[r][v] = base + (slot / 3) * ncx + (slot % 3);
+            }
         }
     }
 
-    // ---- labels, then runs of equal cells into the LDS bins.  A run's
-    // positions are summed as the pixels' offsets inside the thread's block
-    // (column v, row r: compile-time constants) with the count, one 32-bit
-    // add per pixel (v in bits 0.., r in bits 20.., the count in bits 28..;
-    // a run has at most 8 pixels), and turned into offsets from the tile's
-    // corner when the run is added: count * (the block's corner) + sums.
+    // ---- labels, then runs of equal cells into the LDS bins
     const float scale = static_cast<float>(1 << kQShift);
-    const unsigned corner = static_cast<unsigned>(tx * VEC) | (static_cast<unsigned>(ty * ROWS) << 20);
-    auto flush = [&](int cell, int rl, int ra, int rb, unsigned rvr) {
-        const unsigned n = rvr >> 28;
-        const unsigned long long lo =
-            static_cast<unsigned long long>(n) * corner + (rvr & 0x0FFFFFFFu);
-        add_bin(bins, cell, rl, ra, rb, lo | (static_cast<unsigned long long>(n) << 40));
-    };
     int run_cell = -1;
     int rl = 0, ra = 0, rb = 0;
-    unsigned rvr = 0;
+    unsigned long long rxyc = 0;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int y = y0 + ty * ROWS + r;
@@ -510,6 +563,8 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         if constexpr (VEC == 4) {
             store_i4(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]],
                      kidx[cellv[r][3]]);
+        } else if constexpr (VEC == 2) {
+            store_i2(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]]);
         } else {
             labels[pi] = kidx[cellv[r][0]];
         }
@@ -519,24 +574,25 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
             const int ql = static_cast<int>(rintf(pl[r][v] * scale));
             const int qa = static_cast<int>(rintf(pa[r][v] * scale));
             const int qb = static_cast<int>(rintf(pb[r][v] * scale));
-            const unsigned inc = static_cast<unsigned>(v) | (static_cast<unsigned>(r) << 20) |
-                                 (1u << 28);
+            const unsigned long long xyc = static_cast<unsigned long long>(x + v - x0) |
+                                           (static_cast<unsigned long long>(y - y0) << 20) |
+                                           (1ull << 40);
             if (cell != run_cell) {
-                if (run_cell >= 0) flush(run_cell, rl, ra, rb, rvr);
+                if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
                 run_cell = cell;
                 rl = ql;
                 ra = qa;
                 rb = qb;
-                rvr = inc;
+                rxyc = xyc;
             } else {
                 rl += ql;
                 ra += qa;
                 rb += qb;
-                rvr += inc;
+                rxyc += xyc;
             }
         }
     }
-    if (run_cell >= 0) flush(run_cell, rl, ra, rb, rvr);
+    if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
     __syncthreads();
     if constexpr (kConv) {
         if (threadIdx.x == 0 && s_shift)
@@ -544,9 +600,8 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     }
 
     // ---- add the workgroup's bins to the global sums
-    for (int i = threadIdx.x; i < nslots; i += kThreads) {
-        if ((i & (RS - 1)) >= ncx) continue;
-        const unsigned long long p = bins[4 * i + 3];
+    for (int i = threadIdx.x; i < ncells; i += kThreads) {
+        const unsigned long long p = bins[3 * ncells + i];
         const long long n = static_cast<long long>(p >> 40);
         if (n == 0) continue;
         const long long sx = static_cast<long long>(p & 0xFFFFFull) + n * x0;
@@ -554,7 +609,7 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         gmem<unsigned long long>* s = reinterpret_cast<gmem<unsigned long long>*>(
             sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
         const unsigned long long add[kSumStride] = {
-            bins[4 * i], bins[4 * i + 1], bins[4 * i + 2], static_cast<unsigned long long>(sx),
+            bins[i], bins[ncells + i], bins[2 * ncells + i], static_cast<unsigned long long>(sx),
             static_cast<unsigned long long>(sy), static_cast<unsigned long long>(n)};
 #pragma unroll
         for (int j = 0; j < kSumStride; ++j)
@@ -634,30 +689,11 @@ __global__ __launch_bounds__(256) void import_centres_kernel(int K, const float*
         cen[static_cast<size_t>(k) * kCenStride + j] = in[5 * static_cast<size_t>(k) + j];
 }
 
-// Row stride of the staged window for step S: 16 slots when the widest
-// window (at most (tile width - 1) / S + 4 cells) fits, else 64.
-template <int VEC, int ROWS>
-int variant_rs(int S) {
-    using Sh = Shape<VEC, ROWS>;
-    return (Sh::kTileW - 1) / S + 4 <= 16 ? 16 : 64;
-}
-
 template <int VEC, int ROWS>
 size_t variant_lds(int S) {
     using Sh = Shape<VEC, ROWS>;
-    return assign_lds_bytes(((Sh::kTileH - 1) / S + 4) * variant_rs<VEC, ROWS>(S));
-}
-
-template <int VEC, int ROWS, int DIST, int RS>
-void launch_mode(const AssignImage& a, const AssignTileMap& map, long long t, const Converge& cv,
-                 dim3 grid, size_t lds, hipStream_t s) {
-    if (map.images) {
-        assign_kernel<VEC, ROWS, DIST, kModeBatch, RS><<<grid, kThreads, lds, s>>>(a, map, t, cv);
-    } else if (cv.ctl) {
-        assign_kernel<VEC, ROWS, DIST, kModeConverge, RS><<<grid, kThreads, lds, s>>>(a, map, t, cv);
-    } else {
-        assign_kernel<VEC, ROWS, DIST, kModeSingle, RS><<<grid, kThreads, lds, s>>>(a, map, t, cv);
-    }
+    // window of cells over any tile: at most (tile - 1)/S + 4 per side
+    return assign_lds_bytes(((Sh::kTileW - 1) / S + 4) * ((Sh::kTileH - 1) / S + 4));
 }
 
 template <int VEC, int ROWS, int DIST>
@@ -672,11 +708,12 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
     }
     KernelTimer timer("assign", s);
     const size_t lds = variant_lds<VEC, ROWS>(min_S);
-    // every image of a batch has S >= min_S, so its windows fit the stride
-    if (variant_rs<VEC, ROWS>(min_S) == 16) {
-        launch_mode<VEC, ROWS, DIST, 16>(a, map, t, cv, grid, lds, s);
+    if (map.images) {
+        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+    } else if (cv.ctl) {
+        assign_kernel<VEC, ROWS, DIST, kModeConverge><<<grid, kThreads, lds, s>>>(a, map, t, cv);
     } else {
-        launch_mode<VEC, ROWS, DIST, 64>(a, map, t, cv, grid, lds, s);
+        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv);
     }
     return hipGetLastError();
 }
@@ -696,6 +733,8 @@ const VariantDesc kVariants[] = {
     {1, 4, variant_lds<1, 4>, {launch_variant<1, 4, 0>, launch_variant<1, 4, 1>}},
     {4, 1, variant_lds<4, 1>, {launch_variant<4, 1, 0>, launch_variant<4, 1, 1>}},
     {4, 2, variant_lds<4, 2>, {launch_variant<4, 2, 0>, launch_variant<4, 2, 1>}},
+    {2, 1, variant_lds<2, 1>, {launch_variant<2, 1, 0>, launch_variant<2, 1, 1>}},
+    {2, 2, variant_lds<2, 2>, {launch_variant<2, 2, 0>, launch_variant<2, 2, 1>}},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -706,7 +745,7 @@ int assign_variant_count() { return kNumVariants; }
 bool assign_variant_shape(int variant, int* vec, int* rows, int* tile_w, int* tile_h) {
     if (variant < 1 || variant > kNumVariants) return false;
     const VariantDesc& d = kVariants[variant - 1];
-    const int tx = d.vec == 1 ? 32 : 16;
+    const int tx = d.vec == 4 ? 16 : 32;
     if (vec) *vec = d.vec;
     if (rows) *rows = d.rows;
     if (tile_w) *tile_w = tx * d.vec;
@@ -718,7 +757,7 @@ bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S) {
     (void)h;
     if (variant < 1 || variant > kNumVariants) return false;
     const VariantDesc& d = kVariants[variant - 1];
-    if (d.vec == 4 && (S % 4 != 0 || w % 4 != 0)) return false;
+    if (d.vec > 1 && (S % d.vec != 0 || w % d.vec != 0)) return false;
     return d.lds(S) <= (64u << 10);
 }
 

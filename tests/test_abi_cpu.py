@@ -121,10 +121,10 @@ def test_no_device_is_an_error_not_a_fallback(abi):
 
 def test_assign_variant_table(abi):
     n = abi.slic_assign_variants()
-    assert n >= 5
+    assert n >= 7
     shapes = [abi.slic_assign_variant_info(v) for v in range(1, n + 1)]
     for vec, rows, tw, th in shapes:
-        assert vec in (1, 4) and rows >= 1 and tw * th == 256 * vec * rows
+        assert vec in (1, 2, 4) and rows >= 1 and tw * th == 256 * vec * rows
     with pytest.raises(abi.SlicError):
         abi.slic_assign_variant_info(0)
     with pytest.raises(abi.SlicError):
@@ -139,6 +139,15 @@ def test_assign_variant_table(abi):
     assert abi.slic_get_assign_variant(640, 480, 16) == vec4[0]
     abi.slic_set_assign_variant(640, 480, 16, 0)
     assert abi.slic_get_assign_variant(640, 480, 16) != 0
+    # 2-wide variants need S % 2 == 0 and width % 2 == 0
+    vec2 = [v for v in range(1, n + 1) if shapes[v - 1][0] == 2]
+    assert vec2
+    with pytest.raises(abi.SlicError):
+        abi.slic_set_assign_variant(641, 480, 16, vec2[0])
+    with pytest.raises(abi.SlicError):
+        abi.slic_set_assign_variant(640, 480, 7, vec2[0])
+    abi.slic_set_assign_variant(640, 480, 6, vec2[0])
+    abi.slic_set_assign_variant(640, 480, 6, 0)
 
 
 def test_noalloc_limit_matches_header_and_is_checked_on_the_host(abi):

@@ -54,7 +54,7 @@ def test_options_match_oracle(slic, color, squared, w, h, S):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_every_variant_of_the_squared_association(slic, variant):
     w, h, S = 200, 130, 8
     img = _img(w, h, 41)
