@@ -763,11 +763,11 @@ bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S) {
 
 int assign_default_variant(int32_t w, int32_t h, int32_t S) {
     const long long n = static_cast<long long>(w) * h;
-    // small frames are latency bound: the most workgroups; larger frames
+    // small frames are latency bound: many workgroups; larger frames
     // amortise the staged centres over more pixels per thread (the
-    // autotuner's picks: 1 at 320x240, 4 at 640x480, 5 at 1920x1080); a
+    // autotuner's picks: 2 at 320x240, 4 at 640x480, 5 at 1920x1080); a
     // shape the step or width does not allow falls back down the table
-    int v = 1;
+    int v = 2;
     if (n >= (1ll << 20))
         v = 5;
     else if (n >= (1ll << 17))

@@ -559,6 +559,12 @@ constexpr int kFusedA2 = kA2N * 16 * kPS;
 constexpr int kFusedW3 = 9 * 16 * kC;            // third layer's weights
 constexpr int kFusedTab = 2 * (kFW + kFH);       // x / S, x % S, y / S, y % S
 constexpr int kFusedLab = 3 * kFW * kFH;         // the tile's own CIELAB, FP32
+// the decode's logits, per wavefront 64 pixels of kFusedLgStride floats (20:
+// the 16-byte reads of 16 consecutive pixels hit distinct banks), in the
+// first hidden layer's region after the largest bins (S = 1)
+constexpr int kFusedLgStride = 20;
+constexpr int kFusedMaxCells = (kFW + 2) * (kFH + 2);
+constexpr int kFusedLgOff = (kFusedMaxCells * 36 + 63) / 64 * 16;  // floats
 constexpr int kFT = 256;                         // threads per workgroup
 constexpr int kFWaves = kFT / 64;                 // wavefronts per workgroup
 constexpr int kFPerCU = 512 / kFT;                // resident workgroups per compute unit
@@ -566,6 +572,8 @@ constexpr int kXSlots = (kXW * kXH + kFT - 1) / kFT; // input pixels per thread
 constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2 + kFusedW3) * sizeof(unsigned short) +
                              kFusedTab * sizeof(int) + kFusedLab * sizeof(float);
 static_assert(kFPerCU * kFusedLds <= 160 * 1024, "the resident workgroups must fit one CU's LDS");
+static_assert((kFusedLgOff + kFWaves * 64 * kFusedLgStride) * 4 <= kFusedA1 * 2,
+              "the decode's logits fit the first hidden layer's region");
 
 struct FusedImage {
     const float *L, *A, *B;
@@ -576,6 +584,21 @@ struct FusedImage {
     long long *sums_acc, *sums_next;
     int tiles_x, n_tiles;
 };
+
+// ReLU of an accumulator tile's four values packed as bf16; zero when the
+// pixel lies outside the image (all_inside: the whole tile's halo is inside,
+// a uniform test that skips the per-lane one).
+__device__ __forceinline__ uint2 relu_pack(const f32x4& a, bool all_inside, bool inside) {
+    float o[4];
+    if (all_inside) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = fmaxf(a[i], 0.0f);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = inside ? fmaxf(a[i], 0.0f) : 0.0f;
+    }
+    return make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
+}
 
 __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, NetWeights wt) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -646,6 +669,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
             }
         }
     };
+    __builtin_amdgcn_s_waitcnt(0);  // the weights and biases are in registers
     if (static_cast<int>(blockIdx.x) < g.n_tiles) prefetch(blockIdx.x);
 
     for (int tile = blockIdx.x; tile < g.n_tiles; tile += gridDim.x) {
@@ -682,36 +706,55 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         if (tile + static_cast<int>(gridDim.x) < g.n_tiles) prefetch(tile + gridDim.x);
         __syncthreads();
 
-        // ---- first layer
-        for (int nt = wave; nt < kA1N; nt += kFWaves) {
-            const int pr = nt * 16 + row;
-            const int p = min(pr, kA1W * kA1H - 1);
-            const int r = p / kA1W, c = p % kA1W;
-            const unsigned short* src = sx + (r * kXW + c) * 4;
-            const uint2 v0 = *reinterpret_cast<const uint2*>(src + xoff0);
-            const uint2 v1 = *reinterpret_cast<const uint2*>(src + xoff1);
-            const uint2 v8 = *reinterpret_cast<const uint2*>(src + (2 * kXW + 2) * 4);
-            const u32x4 bw = {v0.x, v0.y, v1.x, v1.y};
-            const u32x4 b8 = {v8.x, v8.y, 0u, 0u};
-            f32x4 acc[2];
+        // ---- first layer, two N-tiles (nt, nt + 4) at a time so that the
+        // second's loads and MFMAs overlap the first's epilogue; a pair past
+        // the region computes a clamped tile and stores nothing
+        for (int nt = wave; nt < kA1N; nt += 2 * kFWaves) {
+            int pr[2], p[2], r[2], c[2];
+            u32x4 bw[2], b8[2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    w1[m][0], __builtin_bit_cast(bf16x8, bw), f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    w1[m][1], __builtin_bit_cast(bf16x8, b8), acc[m], 0, 0, 0);
+            for (int u = 0; u < 2; ++u) {
+                pr[u] = (nt + u * kFWaves) * 16 + row;
+                p[u] = min(pr[u], kA1W * kA1H - 1);
+                r[u] = p[u] / kA1W;
+                c[u] = p[u] - r[u] * kA1W;
+                // input pixel (r, c) is p + 2 r: rows of the input region are
+                // two pixels longer (written so, the offset is two adds; a
+                // multiply-add here became a 64-bit one whose unused high
+                // half waited for the next tile's pending loads)
+                static_assert(kXW == kA1W + 2, "input rows are two pixels longer");
+                const unsigned short* src = sx + (p[u] + 2 * r[u]) * 4;
+                const uint2 v0 = *reinterpret_cast<const uint2*>(src + xoff0);
+                const uint2 v1 = *reinterpret_cast<const uint2*>(src + xoff1);
+                const uint2 v8 = *reinterpret_cast<const uint2*>(src + (2 * kXW + 2) * 4);
+                bw[u] = u32x4{v0.x, v0.y, v1.x, v1.y};
+                b8[u] = u32x4{v8.x, v8.y, 0u, 0u};
             }
-            const int gx = x0 - 2 + c, gy = y0 - 2 + r;
-            const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
-            if (pr < kA1W * kA1H) {
+            f32x4 acc[2][2];
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    float o[4];
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        o[i] = inside ? fmaxf(acc[m][i] + bias1[m][i], 0.0f) : 0.0f;
-                    *reinterpret_cast<uint2*>(sa1 + p * kPS + m * 16 + kq * 4) =
-                        make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
+                for (int m = 0; m < 2; ++m)
+                    acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        w1[m][0], __builtin_bit_cast(bf16x8, bw[u]),
+                        f32x4{bias1[m][0], bias1[m][1], bias1[m][2], bias1[m][3]}, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        w1[m][1], __builtin_bit_cast(bf16x8, b8[u]), acc[u][m], 0, 0, 0);
+            // ReLU (the bias started the accumulator); zero outside the image
+            // (tiles whose halo lies inside skip that test)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int gx = x0 - 2 + c[u], gy = y0 - 2 + r[u];
+                const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
+                if (pr[u] < kA1W * kA1H) {
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+                        *reinterpret_cast<uint2*>(sa1 + p[u] * kPS + m * 16 + kq * 4) =
+                            relu_pack(acc[u][m], interior, inside);
                 }
             }
         }
@@ -720,20 +763,25 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         // ---- second layer over the 1-pixel halo, two N-tiles at a time
         for (int pp = wave; 2 * pp < kA2N; pp += kFWaves) {
             int pr[2], r[2], c[2];
+            const unsigned short* base[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 pr[u] = (2 * pp + u) * 16 + row;
                 const int p = min(pr[u], kA2W * kA2H - 1);
                 r[u] = p / kA2W;
-                c[u] = p % kA2W;
+                c[u] = p - r[u] * kA2W;
+                // first-layer pixel (r, c) is p + 2 r (see the first layer)
+                static_assert(kA1W == kA2W + 2, "first-layer rows are two pixels longer");
+                // a 24-bit multiply: a plain one became a 64-bit
+                // multiply-add whose unused high half waited for pending loads
+                base[u] = sa1 + __umul24(static_cast<unsigned>(p + 2 * r[u]), kPS) + kq * 8;
             }
-            const unsigned short* base[2] = {sa1 + (r[0] * kA1W + c[0]) * kPS + kq * 8,
-                                             sa1 + (r[1] * kA1W + c[1]) * kPS + kq * 8};
             f32x4 acc[2][2];
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int m = 0; m < 2; ++m) acc[u][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int m = 0; m < 2; ++m)
+                    acc[u][m] = f32x4{bias2[m][0], bias2[m][1], bias2[m][2], bias2[m][3]};
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
 #pragma unroll
@@ -751,14 +799,9 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
                 const int gx = x0 - 1 + c[u], gy = y0 - 1 + r[u];
                 const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    float o[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        o[i] = inside ? fmaxf(acc[u][m][i] + bias2[m][i], 0.0f) : 0.0f;
+                for (int m = 0; m < 2; ++m)
                     *reinterpret_cast<uint2*>(sa2 + pr[u] * kPS + m * 16 + kq * 4) =
-                        make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
-                }
+                        relu_pack(acc[u][m], interior, inside);
             }
         }
         __syncthreads();
@@ -770,9 +813,15 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
         unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
         int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
+        unsigned long long* const bins1 = bins + ncells;
+        unsigned long long* const bins2 = bins + 2 * ncells;
+        unsigned long long* const bins3 = bins + 3 * ncells;
         for (int i = threadIdx.x; i < ncells; i += kFT) {
             const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
-            for (int j = 0; j < 4; ++j) bins[j * ncells + i] = 0ull;
+            bins[i] = 0ull;
+            bins1[i] = 0ull;
+            bins2[i] = 0ull;
+            bins3[i] = 0ull;
             const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
             const int k = in_grid ? cy * g.ns_c + cx : -1;
             kidx[i] = k;
@@ -783,20 +832,26 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         }
         __syncthreads();
 
-        // ---- third layer, phase bias, argmax, decode, accumulate
+        // ---- third layer, then one pixel per lane: phase bias, argmax,
+        // decode, accumulate.  Wave w's output N-tiles are w, w + 4, w + 8,
+        // w + 12, each pixel's classes spread over four lanes (kq); a round
+        // trip through LDS, written and read by the same wave (whose LDS
+        // operations complete in order), gives lane (row, kq) the logits of
+        // pixel (w + 4 kq) 16 + row, so that every lane decodes one pixel.
         static_assert(kON % kFWaves == 0, "output tiles split evenly over the wavefronts");
         constexpr int kPer = kON / kFWaves;
-        float pb[kPer][4];  // b3 + P of this lane's classes, loaded before the MFMAs
+        static_assert(kPer == 4, "one decoded pixel per lane");
+        const int dp = (wave + kFWaves * kq) * 16 + row;
+        const int dr = dp / kFW, dc = dp % kFW;
+        // the pixel's phase bias, loaded before the MFMAs
+        const int ph = tab[2 * kFW + kFH + dr] * S + tab[kFW + dc];
+        float pP[kC3], pB[kC3];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int p = (wave + kFWaves * u) * 16 + row;
-            const int ph = tab[2 * kFW + kFH + p / kFW] * S + tab[kFW + p % kFW];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = kq * 4 + i;
-                pb[u][i] = o < kC3 ? g.b3[o] + g.P[ph * kC3 + o] : 0.0f;
-            }
+        for (int o = 0; o < kC3; ++o) {
+            pP[o] = g.P[ph * kC3 + o];
+            pB[o] = g.b3[o];
         }
+        __builtin_amdgcn_sched_barrier(0);  // issued here, not next to their use
         f32x4 accs[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) accs[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -808,67 +863,67 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
             for (int u = 0; u < kPer; ++u) {
                 // output pixel p = (wave + 4 u) * 16 + row; rows of 32 hold two N-tiles
                 const int p = (wave + kFWaves * u) * 16 + row;
-                const unsigned short* bp = sa2 + ((p / kFW) * kA2W + p % kFW) * kPS + kq * 8;
+                static_assert(kA2W == kFW + 2, "second-layer rows are two pixels longer");
+                const unsigned short* bp = sa2 + (p + 2 * (p / kFW)) * kPS + kq * 8;
                 const bf16x8 b = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const u32x4*>(bp + ((t / 3) * kA2W + t % 3) * kPS));
                 accs[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, b, accs[u], 0, 0, 0);
             }
         }
+        // the phase bias has arrived: waiting here, on every path, keeps
+        // the compiler from waiting for it (and for the next tile's input)
+        // in the next tile's first layer
+        __builtin_amdgcn_sched_barrier(0);  // the wait stays after the MFMAs
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        float* lgw = reinterpret_cast<float*>(sa1) + kFusedLgOff + wave * 64 * kFusedLgStride;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int p = (wave + kFWaves * u) * 16 + row;
-            const int r = p / kFW, c = p % kFW;
-            const int x = x0 + c, y = y0 + r;
-            // this lane's classes 4 kq .. 4 kq + 3: best value, lowest class on ties
-            float bv = -__builtin_huge_valf();
-            int bc = 15;
+        for (int u = 0; u < kPer; ++u)
+            *reinterpret_cast<f32x4*>(lgw + (u * 16 + row) * kFusedLgStride + kq * 4) = accs[u];
+        const float* mine = lgw + (kq * 16 + row) * kFusedLgStride;
+        const f32x4 q0 = *reinterpret_cast<const f32x4*>(mine);
+        const f32x4 q1 = *reinterpret_cast<const f32x4*>(mine + 4);
+        const float q8 = mine[8];
+        const float lv[kC3] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q8};
+        float v[kC3];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = kq * 4 + i;
-                if (o < kC3) {
-                    const float v = accs[u][i] + pb[u][i];
-                    if (v > bv) {
-                        bv = v;
-                        bc = o;
-                    }
+        for (int o = 0; o < kC3; ++o) v[o] = lv[o] + (pB[o] + pP[o]);
+        // best class, the lowest on ties; its softmax probability is 1 / se
+        float bv = v[0];
+        int bc = 0;
+#pragma unroll
+        for (int o = 1; o < kC3; ++o) {
+            if (v[o] > bv) {
+                bv = v[o];
+                bc = o;
+            }
+        }
+        float se = 0.0f;
+#pragma unroll
+        for (int o = 0; o < kC3; ++o) se += __expf(v[o] - bv);
+        {
+            const int x = x0 + dc, y = y0 + dr;
+            if (x < g.w && y < g.h) {
+                const int cy = min(max(tab[2 * kFW + dr] + bc / 3 - 1, 0), g.ns_r - 1);
+                const int cx = min(max(tab[dc] + bc % 3 - 1, 0), g.ns_c - 1);
+                g.labels[static_cast<size_t>(y) * g.w + x] = cy * g.ns_c + cx;
+                // the pixel votes in the first update when its best class's
+                // probability reaches the prepared minimum confidence
+                if (se * tau <= 1.0f) {
+                    const int cell = (cy - gy_lo) * ncx + (cx - gx_lo);
+                    const float* lab = slab + dp * 3;
+                    // |v| 2^18 < 2^31 for every CIELAB value
+                    const int ql = static_cast<int>(rintf(lab[0] * scale));
+                    const int qa = static_cast<int>(rintf(lab[1] * scale));
+                    const int qb = static_cast<int>(rintf(lab[2] * scale));
+                    atomicAdd(bins + cell, static_cast<unsigned long long>(static_cast<long long>(ql)));
+                    atomicAdd(bins + ncells + cell,
+                              static_cast<unsigned long long>(static_cast<long long>(qa)));
+                    atomicAdd(bins + 2 * ncells + cell,
+                              static_cast<unsigned long long>(static_cast<long long>(qb)));
+                    atomicAdd(bins + 3 * ncells + cell,
+                              static_cast<unsigned long long>(dc) |
+                                  (static_cast<unsigned long long>(dr) << 20) | (1ull << 40));
                 }
-            }
-#pragma unroll
-            for (int sh = 16; sh <= 32; sh <<= 1) {
-                const float ov = __shfl_xor(bv, sh);
-                const int oc = __shfl_xor(bc, sh);
-                if (ov > bv || (ov == bv && oc < bc)) {
-                    bv = ov;
-                    bc = oc;
-                }
-            }
-            // the pixel's best class has softmax probability 1 / se; it votes
-            // in the first update when that reaches the minimum confidence
-            float se = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = kq * 4 + i;
-                if (o < kC3) se += __expf(accs[u][i] + pb[u][i] - bv);
-            }
-            se += __shfl_xor(se, 16);
-            se += __shfl_xor(se, 32);
-            if (kq == 0 && x < g.w && y < g.h) {
-                const int cy = min(max(tab[2 * kFW + r] + bc / 3 - 1, 0), g.ns_r - 1);
-                const int cx = min(max(tab[c] + bc % 3 - 1, 0), g.ns_c - 1);
-                const size_t pi = static_cast<size_t>(y) * g.w + x;
-                g.labels[pi] = cy * g.ns_c + cx;
-                if (!(se * tau <= 1.0f)) continue;
-                const int cell = (cy - gy_lo) * ncx + (cx - gx_lo);
-                const float* lab = slab + p * 3;
-                atomicAdd(bins + cell, static_cast<unsigned long long>(
-                                           static_cast<long long>(rintf(lab[0] * scale))));
-                atomicAdd(bins + ncells + cell, static_cast<unsigned long long>(
-                                                    static_cast<long long>(rintf(lab[1] * scale))));
-                atomicAdd(bins + 2 * ncells + cell, static_cast<unsigned long long>(
-                                                        static_cast<long long>(rintf(lab[2] * scale))));
-                atomicAdd(bins + 3 * ncells + cell,
-                          static_cast<unsigned long long>(c) |
-                              (static_cast<unsigned long long>(r) << 20) | (1ull << 40));
             }
         }
         __syncthreads();
