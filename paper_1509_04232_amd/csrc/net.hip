@@ -676,6 +676,30 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         const int x0 = (tile % g.tiles_x) * kFW, y0 = (tile / g.tiles_x) * kFH;
         // every halo pixel inside the image: no padding checks in the epilogues
         const bool interior = x0 >= 3 && y0 >= 3 && x0 + kFW + 3 <= g.w && y0 + kFH + 3 <= g.h;
+        // the tile's window of grid cells and its LDS bins for the decoded
+        // labels (sums of L, a, b, packed x | y | count, and the cluster of
+        // each cell): in the input region when they fit (cleared during the
+        // second layer, whose barrier then covers them), else in the first
+        // hidden layer's region after the second layer (one more barrier)
+        const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
+        const int gx_hi = (min(x0 + kFW, g.w) - 1) / S + 1;
+        const int gy_hi = (min(y0 + kFH, g.h) - 1) / S + 1;
+        const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
+        const bool early_bins = ncells * 36 <= kFusedX * static_cast<int>(sizeof(unsigned short));
+        unsigned long long* const bins = reinterpret_cast<unsigned long long*>(early_bins ? sx : sa1);
+        int* const kidx = reinterpret_cast<int*>(bins + 4 * ncells);
+        auto init_bins = [&]() {
+            for (int i = threadIdx.x; i < ncells; i += kFT) {
+                const int cy = i / ncx, cx = i - cy * ncx;
+                bins[i] = 0ull;
+                bins[ncells + i] = 0ull;
+                bins[2 * ncells + i] = 0ull;
+                bins[3 * ncells + i] = 0ull;
+                const int gx = gx_lo + cx, gy = gy_lo + cy;
+                const bool in_grid = gx >= 0 && gy >= 0 && gx < g.ns_c && gy < g.ns_r;
+                kidx[i] = in_grid ? gy * g.ns_c + gx : -1;
+            }
+        };
         __syncthreads();  // the previous tile's bins are flushed
 
         // ---- input region (bf16 L/100, a/128, b/128, 0), the tile's own
@@ -760,6 +784,8 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         }
         __syncthreads();
 
+        if (early_bins) init_bins();
+
         // ---- second layer over the 1-pixel halo, two N-tiles at a time
         for (int pp = wave; 2 * pp < kA2N; pp += kFWaves) {
             int pr[2], r[2], c[2];
@@ -806,31 +832,12 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         }
         __syncthreads();
 
-        // ---- LDS bins for the decoded labels (over the first layer's region)
-        const int gx_lo = x0 / S - 1, gy_lo = y0 / S - 1;
-        const int gx_hi = (min(x0 + kFW, g.w) - 1) / S + 1;
-        const int gy_hi = (min(y0 + kFH, g.h) - 1) / S + 1;
-        const int ncx = gx_hi - gx_lo + 1, ncy = gy_hi - gy_lo + 1, ncells = ncx * ncy;
-        unsigned long long* bins = reinterpret_cast<unsigned long long*>(sa1);
-        int* kidx = reinterpret_cast<int*>(bins + 4 * ncells);
-        unsigned long long* const bins1 = bins + ncells;
-        unsigned long long* const bins2 = bins + 2 * ncells;
-        unsigned long long* const bins3 = bins + 3 * ncells;
-        for (int i = threadIdx.x; i < ncells; i += kFT) {
-            const int cx = gx_lo + i % ncx, cy = gy_lo + i / ncx;
-            bins[i] = 0ull;
-            bins1[i] = 0ull;
-            bins2[i] = 0ull;
-            bins3[i] = 0ull;
-            const bool in_grid = cx >= 0 && cy >= 0 && cx < g.ns_c && cy < g.ns_r;
-            const int k = in_grid ? cy * g.ns_c + cx : -1;
-            kidx[i] = k;
-            if (in_grid && (cx * S) / kFW == x0 / kFW && (cy * S) / kFH == y0 / kFH) {
-                long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
-                for (int j = 0; j < kSumStride; ++j) z[j] = 0;
-            }
+        // bins of a large window: cleared now, in the first hidden layer's
+        // region (the second layer has read it)
+        if (!early_bins) {
+            init_bins();
+            __syncthreads();
         }
-        __syncthreads();
 
         // ---- third layer, then one pixel per lane: phase bias, argmax,
         // decode, accumulate.  Wave w's output N-tiles are w, w + 4, w + 8,
@@ -928,6 +935,16 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         }
         __syncthreads();
         for (int i = threadIdx.x; i < ncells; i += kFT) {
+            // the tile holding a cell's first pixel clears that cluster's
+            // next accumulator
+            const int k = kidx[i];
+            if (k >= 0) {
+                const int cx = k % g.ns_c, cy = k / g.ns_c;
+                if ((cx * S) / kFW == x0 / kFW && (cy * S) / kFH == y0 / kFH) {
+                    long long* z = g.sums_next + static_cast<size_t>(k) * kSumStride;
+                    for (int j = 0; j < kSumStride; ++j) z[j] = 0;
+                }
+            }
             const unsigned long long pk = bins[3 * ncells + i];
             const long long cnt = static_cast<long long>(pk >> 40);
             if (cnt == 0) continue;
