@@ -180,9 +180,11 @@ def _decisive_params(S, seed):
     return p
 
 
+# S = 2 and 1: a tile's window of cells is too large for the input region, so
+# the fused kernel keeps the decode bins in the first hidden layer's region
 @pytest.mark.parametrize("w,h,S,perturb,iters", [
     (97, 61, 8, True, 2), (130, 77, 5, False, 3), (64, 64, 16, True, 1), (150, 90, 8, True, 0),
-    (33, 17, 4, True, 4)])
+    (33, 17, 4, True, 4), (70, 45, 2, True, 2), (41, 23, 1, False, 1)])
 def test_warm_segment_matches_oracle(slic, w, h, S, perturb, iters):
     img, lab = _image(w, h, 40 + S)
     p = _decisive_params(S, 50 + w)
@@ -218,7 +220,7 @@ def _two_level_params(S, seed):
 
 @pytest.mark.parametrize("w,h,S,perturb,iters", [
     (97, 61, 8, True, 2), (130, 77, 5, False, 3), (64, 64, 16, True, 1), (150, 90, 8, True, 0),
-    (33, 17, 4, True, 4)])
+    (33, 17, 4, True, 4), (70, 45, 2, True, 2)])
 def test_warm_segment_with_votes_matches_oracle(slic, w, h, S, perturb, iters):
     """A minimum confidence between the two levels: only the confident
     pixels vote in the first update, exactly as the oracle's composition
