@@ -585,19 +585,20 @@ struct FusedImage {
     int tiles_x, n_tiles;
 };
 
-// ReLU of an accumulator tile's four values packed as bf16; zero when the
-// pixel lies outside the image (all_inside: the whole tile's halo is inside,
-// a uniform test that skips the per-lane one).
-__device__ __forceinline__ uint2 relu_pack(const f32x4& a, bool all_inside, bool inside) {
-    float o[4];
-    if (all_inside) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = fmaxf(a[i], 0.0f);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = inside ? fmaxf(a[i], 0.0f) : 0.0f;
-    }
-    return make_uint2(pack2(o[0], o[1]), pack2(o[2], o[3]));
+// ReLU of an accumulator tile's four values packed as bf16, zero when the
+// pixel lies outside the image (keep = 0; else keep = ~0).  The ReLU is
+// applied to the rounded bf16 values as 16-bit integers (a negative value
+// has the sign bit set, so an integer maximum with 0 clears it): the same
+// result as rounding the ReLU of the FP32 value, in one packed integer
+// maximum per two values, where an FP32 maximum in IEEE mode would first
+// quiet each input.
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned relu_bf16x2(unsigned v) {
+    const i16x2 r = __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), i16x2{0, 0});
+    return __builtin_bit_cast(unsigned, r);
+}
+__device__ __forceinline__ uint2 relu_pack(const f32x4& a, unsigned keep) {
+    return make_uint2(relu_bf16x2(pack2(a[0], a[1])) & keep, relu_bf16x2(pack2(a[2], a[3])) & keep);
 }
 
 __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, NetWeights wt) {
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
 #pragma unroll
                     for (int m = 0; m < 2; ++m)
                         *reinterpret_cast<uint2*>(sa1 + p[u] * kPS + m * 16 + kq * 4) =
-                            relu_pack(acc[u][m], interior, inside);
+                            relu_pack(acc[u][m], inside ? ~0u : 0u);
                 }
             }
         }
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
 #pragma unroll
                 for (int m = 0; m < 2; ++m)
                     *reinterpret_cast<uint2*>(sa2 + pr[u] * kPS + m * 16 + kq * 4) =
-                        relu_pack(acc[u][m], interior, inside);
+                        relu_pack(acc[u][m], inside ? ~0u : 0u);
             }
         }
         __syncthreads();
