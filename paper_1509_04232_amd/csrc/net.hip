@@ -592,13 +592,18 @@ struct FusedImage {
 // result as rounding the ReLU of the FP32 value, in one packed integer
 // maximum per two values, where an FP32 maximum in IEEE mode would first
 // quiet each input.
+// The pair is converted by one v_cvt_pk_bf16_f32 written out: through the
+// vector type the compiler converts each value alone and merges the halves
+// (three instructions) once the result is read as 16-bit integers.
 typedef short i16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ unsigned relu_bf16x2(unsigned v) {
+__device__ __forceinline__ unsigned relu_bf16x2(float lo, float hi) {
+    unsigned v;
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(v) : "v"(lo), "v"(hi));
     const i16x2 r = __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), i16x2{0, 0});
     return __builtin_bit_cast(unsigned, r);
 }
 __device__ __forceinline__ uint2 relu_pack(const f32x4& a, unsigned keep) {
-    return make_uint2(relu_bf16x2(pack2(a[0], a[1])) & keep, relu_bf16x2(pack2(a[2], a[3])) & keep);
+    return make_uint2(relu_bf16x2(a[0], a[1]) & keep, relu_bf16x2(a[2], a[3]) & keep);
 }
 
 __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, NetWeights wt) {
