@@ -814,17 +814,39 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
 #pragma unroll
                 for (int m = 0; m < 2; ++m)
                     acc[u][m] = f32x4{bias2[m][0], bias2[m][1], bias2[m][2], bias2[m][3]};
+            // operands three taps ahead, so that each LDS read has the MFMAs
+            // of two taps (eight) to arrive in
+            auto operand = [&](int t, int u) {
+                return __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(base[u] + ((t / 3) * kA1W + t % 3) * kPS));
+            };
+            constexpr int kAhead = 3;
+            bf16x8 bq[kAhead][2];
+#pragma unroll
+            for (int t = 0; t < kAhead; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) bq[t][u] = operand(t, u);
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const bf16x8 b = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const u32x4*>(base[u] + ((t / 3) * kA1W + t % 3) * kPS));
+                    const bf16x8 b = bq[t % kAhead][u];
 #pragma unroll
                     for (int m = 0; m < 2; ++m)
                         acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][m], b, acc[u][m], 0, 0, 0);
+                    if (t + kAhead < 9) bq[t % kAhead][u] = operand(t + kAhead, u);
                 }
             }
+            // the schedule: six reads, then four MFMAs and two reads six
+            // times, then the last twelve MFMAs (left alone, the compiler
+            // keeps only two reads in flight)
+            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (2 * pp + u >= kA2N) break;
@@ -883,6 +905,15 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
                 accs[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, b, accs[u], 0, 0, 0);
             }
         }
+        // the schedule: the operands of one tap (five reads) first, then
+        // each tap's four MFMAs followed by the reads of the next tap
+        __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         // the phase bias has arrived: waiting here, on every path, keeps
         // the compiler from waiting for it (and for the next tile's input)
         // in the next tile's first layer
