@@ -32,6 +32,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "slic_internal.h"
@@ -736,14 +737,15 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         if (tile + static_cast<int>(gridDim.x) < g.n_tiles) prefetch(tile + gridDim.x);
         __syncthreads();
 
-        // ---- first layer, two N-tiles (nt, nt + 4) at a time so that the
-        // second's loads and MFMAs overlap the first's epilogue; a pair past
-        // the region computes a clamped tile and stores nothing
-        for (int nt = wave; nt < kA1N; nt += 2 * kFWaves) {
-            int pr[2], p[2], r[2], c[2];
-            u32x4 bw[2], b8[2];
+        // ---- first layer: N-tiles nt, nt + 4, ... of the wave, two at a time
+        // (so that the second's loads and MFMAs overlap the first's
+        // epilogue) while two remain, then a last one alone
+        auto layer1 = [&](int nt, auto count) {
+            constexpr int kN = decltype(count)::value;
+            int pr[kN], p[kN], r[kN], c[kN];
+            u32x4 bw[kN], b8[kN];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < kN; ++u) {
                 pr[u] = (nt + u * kFWaves) * 16 + row;
                 p[u] = min(pr[u], kA1W * kA1H - 1);
                 r[u] = p[u] / kA1W;
@@ -760,16 +762,16 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
                 bw[u] = u32x4{v0.x, v0.y, v1.x, v1.y};
                 b8[u] = u32x4{v8.x, v8.y, 0u, 0u};
             }
-            f32x4 acc[2][2];
+            f32x4 acc[kN][2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < kN; ++u)
 #pragma unroll
                 for (int m = 0; m < 2; ++m)
                     acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         w1[m][0], __builtin_bit_cast(bf16x8, bw[u]),
                         f32x4{bias1[m][0], bias1[m][1], bias1[m][2], bias1[m][3]}, 0, 0, 0);
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < kN; ++u)
 #pragma unroll
                 for (int m = 0; m < 2; ++m)
                     acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
@@ -777,7 +779,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
             // ReLU (the bias started the accumulator); zero outside the image
             // (tiles whose halo lies inside skip that test)
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < kN; ++u) {
                 const int gx = x0 - 2 + c[u], gy = y0 - 2 + r[u];
                 const bool inside = interior || (gx >= 0 && gy >= 0 && gx < g.w && gy < g.h);
                 if (pr[u] < kA1W * kA1H) {
@@ -787,7 +789,10 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
                             relu_pack(acc[u][m], inside ? ~0u : 0u);
                 }
             }
-        }
+        };
+        int nt1 = wave;
+        for (; nt1 + kFWaves < kA1N; nt1 += 2 * kFWaves) layer1(nt1, std::integral_constant<int, 2>{});
+        if (nt1 < kA1N) layer1(nt1, std::integral_constant<int, 1>{});
         __syncthreads();
 
         if (early_bins) init_bins();
