@@ -539,14 +539,14 @@ __global__ void export_logits_kernel(const float* __restrict__ lg16, long long t
 // the image are zero, which is the zero padding of every layer.  The first
 // layer takes K over (tap, channel) pairs with the input stored as 4
 // channels (the fourth zero): taps 0..7 in one MFMA, tap 8 in a second.
-// Workgroups are persistent: each loads the weights once (the first two
-// layers into registers, the third into LDS) and walks tiles blockIdx.x,
-// + gridDim.x, ...  The logits stay in registers: the argmax combines the
-// four lanes that hold a pixel's classes, and the decoded label enters the
-// cluster sums as in the association kernel (LDS bins, then one global add
-// per non-empty bin) if the pixel votes (its best class's softmax
-// probability reaches the prepared minimum confidence); the workgroup
-// holding a cell's first pixel clears that cluster's next accumulator.
+// Workgroups are persistent: each loads the weights of all three layers into
+// registers once and walks tiles blockIdx.x, + gridDim.x, ...  The logits
+// pass through LDS so that each lane decodes one pixel: argmax, label, and
+// the pixel enters the cluster sums as in the association kernel (LDS bins,
+// then one global add per non-empty bin) if it votes (its best class's
+// softmax probability reaches the prepared minimum confidence); the
+// workgroup holding a cell's first pixel clears that cluster's next
+// accumulator.
 constexpr int kFW = 32, kFH = 8;
 constexpr int kXW = kFW + 6, kXH = kFH + 6;      // input region
 constexpr int kA1W = kFW + 4, kA1H = kFH + 4;    // first hidden layer region
@@ -557,7 +557,6 @@ constexpr int kON = kFW * kFH / 16;
 constexpr int kFusedX = kXW * kXH * 4;           // u16 elements
 constexpr int kFusedA1 = kA1W * kA1H * kPS;
 constexpr int kFusedA2 = kA2N * 16 * kPS;
-constexpr int kFusedW3 = 9 * 16 * kC;            // third layer's weights
 constexpr int kFusedTab = 2 * (kFW + kFH);       // x / S, x % S, y / S, y % S
 constexpr int kFusedLab = 3 * kFW * kFH;         // the tile's own CIELAB, FP32
 // the decode's logits, per wavefront 64 pixels of kFusedLgStride floats (20:
@@ -570,7 +569,7 @@ constexpr int kFT = 256;                         // threads per workgroup
 constexpr int kFWaves = kFT / 64;                 // wavefronts per workgroup
 constexpr int kFPerCU = 512 / kFT;                // resident workgroups per compute unit
 constexpr int kXSlots = (kXW * kXH + kFT - 1) / kFT; // input pixels per thread
-constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2 + kFusedW3) * sizeof(unsigned short) +
+constexpr size_t kFusedLds = (kFusedX + kFusedA1 + kFusedA2) * sizeof(unsigned short) +
                              kFusedTab * sizeof(int) + kFusedLab * sizeof(float);
 static_assert(kFPerCU * kFusedLds <= 160 * 1024, "the resident workgroups must fit one CU's LDS");
 static_assert((kFusedLgOff + kFWaves * 64 * kFusedLgStride) * 4 <= kFusedA1 * 2,
@@ -612,16 +611,19 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
     unsigned short* sx = reinterpret_cast<unsigned short*>(smem);
     unsigned short* sa1 = sx + kFusedX;
     unsigned short* sa2 = sa1 + kFusedA1;
-    unsigned short* sw3 = sa2 + kFusedA2;
-    int* tab = reinterpret_cast<int*>(sw3 + kFusedW3);
+    int* tab = reinterpret_cast<int*>(sa2 + kFusedA2);
     float* slab = reinterpret_cast<float*>(tab + kFusedTab);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int S = g.S;
 
     // ---- weights and biases, once per workgroup
-    for (int i = threadIdx.x; i < kFusedW3 / 8; i += kFT)
-        reinterpret_cast<u32x4*>(sw3)[i] = reinterpret_cast<const u32x4*>(wt.W3b)[i];
+    // third layer's weights in registers, one 16 x 32 fragment per tap
+    bf16x8 w3r[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+        w3r[t] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const u32x4*>(wt.W3b + (t * 16 + row) * kC + kq * 8));
     // first layer: A[o][k] with k = 4 tap + c for taps 0..7, and tap 8 alone
     bf16x8 w1[2][2], w2[9][2];
 #pragma unroll
@@ -897,8 +899,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
         for (int u = 0; u < kPer; ++u) accs[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const bf16x8 w3 = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(sw3 + (t * 16 + row) * kC + kq * 8));
+            const bf16x8 w3 = w3r[t];
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 // output pixel p = (wave + 4 u) * 16 + row; rows of 32 hold two N-tiles
@@ -910,13 +911,13 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
                 accs[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, b, accs[u], 0, 0, 0);
             }
         }
-        // the schedule: the operands of one tap (five reads) first, then
+        // the schedule: the operands of one tap (four reads) first, then
         // each tap's four MFMAs followed by the reads of the next tap
-        __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
         }
         __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         // the phase bias has arrived: waiting here, on every path, keeps
