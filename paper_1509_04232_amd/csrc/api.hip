@@ -172,23 +172,36 @@ int check_buffers(const void* rgb, const void* ws) {
     return check_device_ptr(ws);
 }
 
-// Section 4's listing up to the first association.
-hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb) {
+// Association launch c->t.  With ccl set and *ccl true (the last launch
+// before the connectivity clean-up), the launch that also finds the
+// tile-local components where the image allows its shape; *ccl then says
+// whether it did.
+hipError_t associate(slic_ctx* c, bool* ccl) {
+    const slic_params& p = c->p;
+    if (ccl && *ccl && !assign_final_ccl_supported(p.width, p.height, c->g.S)) *ccl = false;
+    if (ccl && *ccl) return launch_assign_final_ccl(c->ws, p.width, p.height, c->g, c->t, c->stream);
+    return launch_assign(c->ws, p.width, p.height, c->g, c->t, c->variant, c->stream);
+}
+
+// Section 4's listing up to the first association (ccl: as in associate,
+// for a first association that is also the last).
+hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb, bool* ccl = nullptr) {
     const slic_params& p = c->p;
     hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
                                    (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
     if (e != hipSuccess) return e;
     c->t = 0;
-    e = launch_assign(c->ws, p.width, p.height, c->g, c->t, c->variant, c->stream);
+    e = associate(c, ccl);
     if (e == hipSuccess) c->t = 1;
     return e;
 }
 
 // n rounds of (update, associate): each association launch also completes
-// the previous launch's centre update.
-hipError_t enqueue_iterations(slic_ctx* c, int32_t n) {
+// the previous launch's centre update (ccl: as in associate, for the last
+// of them; untouched when n is 0).
+hipError_t enqueue_iterations(slic_ctx* c, int32_t n, bool* ccl = nullptr) {
     for (int32_t i = 0; i < n; ++i) {
-        hipError_t e = launch_assign(c->ws, c->p.width, c->p.height, c->g, c->t, c->variant, c->stream);
+        hipError_t e = associate(c, i == n - 1 ? ccl : nullptr);
         if (e != hipSuccess) return e;
         ++c->t;
     }
@@ -468,15 +481,18 @@ int enqueue_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters,
     slic_ctx c;
     bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;  // associate straight into the caller's buffer
-    if (enqueue_init(&c, d_rgb) != hipSuccess) return SLIC_EHIP;
-    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
+    // the last association also finds the tile-local components, if it can
+    bool local_done = enforce != 0;
+    if (enqueue_init(&c, d_rgb, n_iters == 0 ? &local_done : nullptr) != hipSuccess)
+        return SLIC_EHIP;
+    if (enqueue_iterations(&c, n_iters, &local_done) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
         launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
         return SLIC_EHIP;
     if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
         return SLIC_EHIP;
     if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
-                                       d_n_segments, c.stream) != hipSuccess)
+                                       d_n_segments, c.stream, local_done) != hipSuccess)
         return SLIC_EHIP;
     return SLIC_OK;
 }
@@ -804,14 +820,16 @@ int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const void* d_
     bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;
     if (enqueue_warm_init(&c, d_rgb, d_net) != hipSuccess) return SLIC_EHIP;
-    if (enqueue_iterations(&c, n_iters) != hipSuccess) return SLIC_EHIP;
+    // with rounds, the last association also finds the tile-local components
+    bool local_done = enforce != 0 && n_iters > 0;
+    if (enqueue_iterations(&c, n_iters, &local_done) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
         launch_energy(c.ws, p->width, p->height, c.g, d_energy, c.stream) != hipSuccess)
         return SLIC_EHIP;
     if (d_centres && launch_export_centres(c.ws, c.g, d_centres, nullptr, c.stream) != hipSuccess)
         return SLIC_EHIP;
     if (enforce && launch_connectivity(c.ws, p->width, p->height, c.g, p->min_segment, d_labels,
-                                       d_n_segments, c.stream) != hipSuccess)
+                                       d_n_segments, c.stream, local_done) != hipSuccess)
         return SLIC_EHIP;
     return SLIC_OK;
 }

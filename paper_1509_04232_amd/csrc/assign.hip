@@ -35,6 +35,7 @@
 // its value), and clears sums[(t + 1) % 3] for the next launch.  The
 // workgroup holding a cell's first pixel owns that centre: it stores the new
 // centre and count and clears the next buffer.
+#include "ccl_tile.h"
 #include "slic_internal.h"
 
 #pragma clang fp contract(off)
@@ -202,16 +203,27 @@ __device__ __forceinline__ float dist_squared(float cl, float ca, float cb, floa
     return s + sp;
 }
 
-// Launch modes: one image, one image with the convergence stop, a batch.
-// Each is its own instantiation, so a kernel reads only the arguments its
-// mode uses and takes no branch on them on the way in.
-enum AssignMode { kModeSingle = 0, kModeConverge = 1, kModeBatch = 2 };
+// Launch modes: one image, one image with the convergence stop, a batch,
+// and one image whose launch is the last before the connectivity clean-up
+// and also finds the tile-local components of its labels (32 x 32 tiles
+// only).  Each is its own instantiation, so a kernel reads only the
+// arguments its mode uses and takes no branch on them on the way in.
+enum AssignMode { kModeSingle = 0, kModeConverge = 1, kModeBatch = 2, kModeFinalCcl = 3 };
+
+// Outputs of the tile-local connectivity step (kModeFinalCcl): every
+// pixel's local root as a global index and as an index inside its tile, and
+// the local roots' part sizes.
+struct AssignCcl {
+    int32_t* comp;
+    int32_t* lroot;
+    int32_t* size;
+};
 
 // The Eq. 1 variants are held to 128 VGPRs (four waves per SIMD), which
 // they need for latency hiding at large frames.
 template <int VEC, int ROWS, int DIST, int MODE>
 __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
-    AssignImage single, AssignTileMap map, long long t, Converge cv) {
+    AssignImage single, AssignTileMap map, long long t, Converge cv, AssignCcl cc) {
     using Sh = Shape<VEC, ROWS>;
     constexpr bool kConv = MODE == kModeConverge;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -615,6 +627,30 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         for (int j = 0; j < kSumStride; ++j)
             __hip_atomic_fetch_add(s + j, add[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+
+    // ---- the tile-local components of the labels just written (the
+    // connectivity pass's first step, on the same 32 x 32 tile), after the
+    // global adds are issued
+    if constexpr (MODE == kModeFinalCcl) {
+        static_assert(VEC == 1 && Sh::kTileW == tile_ccl::kTile && Sh::kTileH == tile_ccl::kTile &&
+                          kThreads == tile_ccl::kBlock,
+                      "the tile-local components need the 32 x 32 connectivity tile");
+        __shared__ int clab[tile_ccl::kTilePx];
+        __shared__ int cpar[tile_ccl::kTilePx];
+        __shared__ int ccnt[tile_ccl::kTilePx];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = y0 + ty * ROWS + r;
+            clab[(ty * ROWS + r) * tile_ccl::kTile + tx] =
+                col_ok && y < g.h ? kidx[cellv[r][0]] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < tile_ccl::kPxPerThread; ++j)
+            ccnt[threadIdx.x + j * tile_ccl::kBlock] = 0;
+        __syncthreads();
+        tile_ccl::tile_components(clab, cpar, ccnt, x0, y0, g.w, g.h, as_global(cc.comp),
+                                  as_global(cc.lroot), as_global(cc.size));
+    }
 }
 
 __global__ void converge_reset_kernel(long long* ctl) {
@@ -709,12 +745,28 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
     KernelTimer timer("assign", s);
     const size_t lds = variant_lds<VEC, ROWS>(min_S);
     if (map.images) {
-        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv, {});
     } else if (cv.ctl) {
-        assign_kernel<VEC, ROWS, DIST, kModeConverge><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+        assign_kernel<VEC, ROWS, DIST, kModeConverge><<<grid, kThreads, lds, s>>>(a, map, t, cv,
+                                                                                 {});
     } else {
-        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv);
+        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv, {});
     }
+    return hipGetLastError();
+}
+
+// The final launch with the tile-local components: the 1 x 4 shape, whose
+// tiles are the connectivity pass's 32 x 32 tiles.
+template <int DIST>
+hipError_t launch_final_ccl(const AssignImage& a, long long t, const AssignCcl& cc, int S,
+                            hipStream_t s) {
+    using Sh = Shape<1, 4>;
+    const dim3 grid((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
+    const AssignTileMap none{nullptr, nullptr, nullptr};
+    const Converge off{nullptr, 0, 0};
+    KernelTimer timer("assign", s);
+    assign_kernel<1, 4, DIST, kModeFinalCcl><<<grid, kThreads, variant_lds<1, 4>(S), s>>>(
+        a, none, t, off, cc);
     return hipGetLastError();
 }
 
@@ -812,6 +864,23 @@ hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     const AssignTileMap none{nullptr, nullptr, nullptr};
     const Converge off{nullptr, 0, 0};
     return kVariants[variant - 1].launch[g.dist ? 1 : 0](a, none, 0, g.S, t, cv ? *cv : off, s);
+}
+
+constexpr int kFinalCclVariant = 3;  // 1 x 4: 32 x 32 tiles
+
+bool assign_final_ccl_supported(int32_t w, int32_t h, int32_t S) {
+    int tw = 0, th = 0;
+    return assign_variant_shape(kFinalCclVariant, nullptr, nullptr, &tw, &th) &&
+           tw == tile_ccl::kTile && th == tile_ccl::kTile &&
+           assign_variant_supported(kFinalCclVariant, w, h, S);
+}
+
+hipError_t launch_assign_final_ccl(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                                  int64_t t, hipStream_t s) {
+    if (!assign_final_ccl_supported(w, h, g.S)) return hipErrorInvalidValue;
+    const AssignImage a = assign_image(ws, w, h, g, kFinalCclVariant);
+    const AssignCcl cc{ws.ccl0, ws.ccl3, ws.ccl1};  // as the connectivity pass names them
+    return g.dist ? launch_final_ccl<1>(a, t, cc, g.S, s) : launch_final_ccl<0>(a, t, cc, g.S, s);
 }
 
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,

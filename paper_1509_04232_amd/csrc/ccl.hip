@@ -17,6 +17,7 @@
 // (with path splitting) by the relabel pass; ballot counts and prefix sums
 // over the surviving roots for the numbering.  All integer, so the result
 // is exact.
+#include "ccl_tile.h"
 #include "slic_internal.h"
 
 namespace slic {
@@ -80,9 +81,10 @@ __device__ void unite(gmem<int>* P, int a, int b) {
 // ---- components in three steps: union-find inside 32 x 32 tiles in LDS,
 // unions across tile borders in global memory, then every pixel resolves its
 // root and the tile adds its pixel counts per root.
-constexpr int kTile = 32;
-constexpr int kTilePx = kTile * kTile;
-constexpr int kPxPerThread = kTilePx / kBlock;
+constexpr int kTile = tile_ccl::kTile;
+constexpr int kTilePx = tile_ccl::kTilePx;
+constexpr int kPxPerThread = tile_ccl::kPxPerThread;
+static_assert(kBlock == tile_ccl::kBlock, "the tile passes use the shared tile shape");
 
 // The image of tile number idx of a launch and the tile's (x, y) among the
 // image's 32 x 32 tiles: from the kernel argument (one image) or, for a
@@ -130,47 +132,10 @@ __device__ __forceinline__ void resolve_block(const CclImage& single, const CclM
     }
 }
 
-__device__ __forceinline__ int lds_load(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ int lds_find(int* P, int x) {
-    int p = lds_load(P + x);
-    while (p != x) {
-        x = p;
-        p = lds_load(P + x);
-    }
-    return x;
-}
-
-__device__ void lds_unite(int* P, int a, int b) {
-    bool done;
-    do {
-        a = lds_find(P, a);
-        b = lds_find(P, b);
-        if (a < b) {
-            const int old = atomicMin(P + b, a);
-            done = old == b;
-            b = old;
-        } else if (b < a) {
-            const int old = atomicMin(P + a, b);
-            done = old == a;
-            a = old;
-        } else {
-            done = true;
-        }
-    } while (!done);
-}
-
-// Tile-local components.  Local indices follow raster order inside the
-// tile, so a local root (the smallest local index) is also the smallest
-// global index of the component's part in the tile.  A wavefront holds two
-// 32-pixel tile rows; each pixel finds the head of its horizontal run of
-// equal labels from a ballot of run starts, and union-find then links run
-// heads only, once per vertical overlap of two runs.  Writes P[i] = global
-// index of i's local root and lroot[i] = its local index; a local root's
-// size entry receives the pixel count of its part of the tile (the run
-// lengths added per run head, far fewer LDS atomics than one per pixel).
+// Tile-local components of the association labels: the tile's labels into
+// LDS, then tile_ccl::tile_components (P, lroot and the local roots' sizes).
+// The association launch that ends a segmentation can do this itself for
+// 32 x 32 tiles; the pass is then skipped.
 template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclMap map) {
     __shared__ int lab[kTilePx];
@@ -201,53 +166,7 @@ __global__ __launch_bounds__(kBlock) void ccl_local_kernel(CclImage single, CclM
         cnt[li] = 0;
     }
     __syncthreads();
-    // every pixel links to the head (first pixel) of its run; a head also
-    // notes its run's length (up to the next run start of the row)
-    const int half = (threadIdx.x & 63) >= 32 ? 32 : 0;  // which row of the wavefront
-    const unsigned upto = col == 31 ? 0xFFFFFFFFu : (2u << col) - 1u;
-    int runlen[kPxPerThread];
-#pragma unroll
-    for (int j = 0; j < kPxPerThread; ++j) {
-        const int li = threadIdx.x + j * kBlock;
-        const bool start = col == 0 || lab[li] != lab[li - 1];
-        const unsigned row_starts = static_cast<unsigned>(__ballot(start) >> half);
-        par[li] = li - col + (31 - __clz(row_starts & upto));
-        const unsigned later = row_starts & ~upto;  // starts right of this column
-        runlen[j] = start ? (later ? __ffs(later) - 1 : kTile) - col : 0;
-    }
-    __syncthreads();
-    for (int j = 0; j < kPxPerThread; ++j) {
-        const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + col, y = y0 + li / kTile;
-        if (x >= w || y >= h || li < kTile) continue;
-        const int v = lab[li];
-        if (lab[li - kTile] != v) continue;
-        // one union per vertical overlap of two runs: at its first column
-        if (col > 0 && lab[li - 1] == v && lab[li - 1 - kTile] == v) continue;
-        lds_unite(par, li, li - kTile);
-    }
-    __syncthreads();
-    int rr[kPxPerThread];
-#pragma unroll
-    for (int j = 0; j < kPxPerThread; ++j) {
-        const int li = threadIdx.x + j * kBlock;
-        const int x = x0 + col, y = y0 + li / kTile;
-        rr[j] = -1;
-        if (x >= w || y >= h) continue;
-        const int r = lds_find(par, li);
-        rr[j] = r;
-        const size_t gi = static_cast<size_t>(y) * w + x;
-        P[gi] = (y0 + r / kTile) * w + x0 + r % kTile;
-        lroot[gi] = r;
-        if (runlen[j] > 0) atomicAdd(cnt + r, runlen[j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPxPerThread; ++j) {
-        const int li = threadIdx.x + j * kBlock;
-        if (rr[j] != li) continue;  // local roots only (pixels inside the image)
-        size[static_cast<size_t>(y0 + li / kTile) * w + x0 + col] = cnt[li];
-    }
+    tile_ccl::tile_components(lab, par, cnt, x0, y0, w, h, P, lroot, size);
 }
 
 // Unions across the left and top borders of every tile.
@@ -660,13 +579,14 @@ bool ccl_batch_supported(int32_t w, int32_t h) { return scan_tiles_for(w * h) <=
 
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
-                               hipStream_t s) {
+                               hipStream_t s, bool local_done) {
     const CclImage c = ccl_image(ws, w, h, g, min_segment, labels_out, n_segments);
     const CclMap none{};
     hipError_t e;
     const int tiles = ccl_tiles_for(w, h);
     const dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
-    SLIC_STEP("ccl_local", ccl_local_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
+    if (!local_done)
+        SLIC_STEP("ccl_local", ccl_local_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
     SLIC_STEP("ccl_border", ccl_border_kernel<false><<<grid, 2 * kTile, 0, s>>>(c, none));
     SLIC_STEP("ccl_flatten", ccl_flatten_kernel<false><<<grid, kBlock, 0, s>>>(c, none));
     SLIC_STEP("ccl_merge",

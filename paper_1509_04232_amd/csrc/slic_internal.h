@@ -117,6 +117,14 @@ hipError_t launch_converge_result(const long long* ctl, int32_t max_iters, int32
 // falls back to assign_default_variant.
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
                          int variant, hipStream_t s, const Converge* cv = nullptr);
+// Association launch t as the last one before the connectivity clean-up:
+// it also writes the clean-up's tile-local components (ws.ccl0, ws.ccl3,
+// ws.ccl1, the connectivity pass's first step), so launch_connectivity then
+// runs with local_done.  Only where assign_final_ccl_supported (the launch
+// has the 1 x 4 shape, whose tiles are the clean-up's 32 x 32 tiles).
+bool assign_final_ccl_supported(int32_t w, int32_t h, int32_t S);
+hipError_t launch_assign_final_ccl(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
+                                  int64_t t, hipStream_t s);
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
                                int variant, int dist, hipStream_t s);
 AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant);
@@ -127,9 +135,11 @@ bool assign_variant_supported(int variant, int32_t w, int32_t h, int32_t S);
 int assign_default_variant(int32_t w, int32_t h, int32_t S);
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,
                          hipStream_t s);
+// local_done: the final association launch already wrote the tile-local
+// components (launch_assign_final_ccl), so the first pass is skipped.
 hipError_t launch_connectivity(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                int32_t min_segment, int32_t* labels_out, int32_t* n_segments,
-                               hipStream_t s);
+                               hipStream_t s, bool local_done = false);
 
 // Connectivity of one image: device pointers into its workspace and sizes.
 struct CclImage {
