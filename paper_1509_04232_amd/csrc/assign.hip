@@ -168,9 +168,9 @@ __host__ __device__ inline size_t assign_lds_bytes(int ncells) {
 // pixels in each of ROWS consecutive rows.  VEC = 2 or 4 uses 8- or 16-byte
 // loads and evaluates each staged centre once for the VEC pixels, so it
 // needs them in one cell (S % VEC == 0) and aligned rows (width % VEC == 0).
-template <int VEC, int ROWS>
+template <int VEC, int ROWS, int TX = (VEC == 4 ? 16 : 32)>
 struct Shape {
-    static constexpr int kTX = VEC == 4 ? 16 : 32;  // threads per row
+    static constexpr int kTX = TX;  // threads per row
     static constexpr int kTY = kThreads / kTX;
     static constexpr int kTileW = kTX * VEC;
     static constexpr int kTileH = kTY * ROWS;
@@ -219,12 +219,18 @@ struct AssignCcl {
     int32_t* size;
 };
 
+// A launch's shape: its variant's, except that the final launch with the
+// tile-local components has the connectivity pass's 32 x 32 tiles.
+template <int VEC, int ROWS, int MODE>
+using LaunchShape =
+    Shape<VEC, ROWS, MODE == kModeFinalCcl ? tile_ccl::kTile / VEC : (VEC == 4 ? 16 : 32)>;
+
 // The Eq. 1 variants are held to 128 VGPRs (four waves per SIMD), which
 // they need for latency hiding at large frames.
 template <int VEC, int ROWS, int DIST, int MODE>
 __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     AssignImage single, AssignTileMap map, long long t, Converge cv, AssignCcl cc) {
-    using Sh = Shape<VEC, ROWS>;
+    using Sh = LaunchShape<VEC, ROWS, MODE>;
     constexpr bool kConv = MODE == kModeConverge;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_shift;
@@ -632,7 +638,7 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
     // connectivity pass's first step, on the same 32 x 32 tile), after the
     // global adds are issued
     if constexpr (MODE == kModeFinalCcl) {
-        static_assert(VEC == 1 && Sh::kTileW == tile_ccl::kTile && Sh::kTileH == tile_ccl::kTile &&
+        static_assert(Sh::kTileW == tile_ccl::kTile && Sh::kTileH == tile_ccl::kTile &&
                           kThreads == tile_ccl::kBlock,
                       "the tile-local components need the 32 x 32 connectivity tile");
         __shared__ int clab[tile_ccl::kTilePx];
@@ -641,8 +647,10 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int y = y0 + ty * ROWS + r;
-            clab[(ty * ROWS + r) * tile_ccl::kTile + tx] =
-                col_ok && y < g.h ? kidx[cellv[r][0]] : -1;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                clab[(ty * ROWS + r) * tile_ccl::kTile + tx * VEC + v] =
+                    col_ok && y < g.h ? kidx[cellv[r][v]] : -1;
         }
 #pragma unroll
         for (int j = 0; j < tile_ccl::kPxPerThread; ++j)
@@ -755,19 +763,32 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
     return hipGetLastError();
 }
 
-// The final launch with the tile-local components: the 1 x 4 shape, whose
-// tiles are the connectivity pass's 32 x 32 tiles.
-template <int DIST>
+// The final launch with the tile-local components, on 32 x 32 tiles: four
+// pixels of a row per thread (VEC = 4, eight threads per row) below 1 Mpix
+// where the step and the width allow it, else one pixel in each of four
+// rows (at 1920 x 1080 the faster of the two, as among the variants).
+template <int VEC, int ROWS>
+size_t final_ccl_lds(int S) {
+    using Sh = LaunchShape<VEC, ROWS, kModeFinalCcl>;
+    return assign_lds_bytes(((Sh::kTileW - 1) / S + 4) * ((Sh::kTileH - 1) / S + 4));
+}
+
+template <int VEC, int ROWS, int DIST>
 hipError_t launch_final_ccl(const AssignImage& a, long long t, const AssignCcl& cc, int S,
                             hipStream_t s) {
-    using Sh = Shape<1, 4>;
+    using Sh = LaunchShape<VEC, ROWS, kModeFinalCcl>;
     const dim3 grid((a.w + Sh::kTileW - 1) / Sh::kTileW, (a.h + Sh::kTileH - 1) / Sh::kTileH);
     const AssignTileMap none{nullptr, nullptr, nullptr};
     const Converge off{nullptr, 0, 0};
     KernelTimer timer("assign", s);
-    assign_kernel<1, 4, DIST, kModeFinalCcl><<<grid, kThreads, variant_lds<1, 4>(S), s>>>(
-        a, none, t, off, cc);
+    assign_kernel<VEC, ROWS, DIST, kModeFinalCcl><<<grid, kThreads, final_ccl_lds<VEC, ROWS>(S),
+                                                     s>>>(a, none, t, off, cc);
     return hipGetLastError();
+}
+
+bool final_ccl_vec4(int32_t w, int32_t h, int32_t S) {
+    return static_cast<long long>(w) * h < (1ll << 20) && S % 4 == 0 && w % 4 == 0 &&
+           final_ccl_lds<4, 1>(S) <= (64u << 10);
 }
 
 using LaunchFn = hipError_t (*)(const AssignImage&, const AssignTileMap&, int, int, long long,
@@ -866,21 +887,23 @@ hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& 
     return kVariants[variant - 1].launch[g.dist ? 1 : 0](a, none, 0, g.S, t, cv ? *cv : off, s);
 }
 
-constexpr int kFinalCclVariant = 3;  // 1 x 4: 32 x 32 tiles
-
 bool assign_final_ccl_supported(int32_t w, int32_t h, int32_t S) {
-    int tw = 0, th = 0;
-    return assign_variant_shape(kFinalCclVariant, nullptr, nullptr, &tw, &th) &&
-           tw == tile_ccl::kTile && th == tile_ccl::kTile &&
-           assign_variant_supported(kFinalCclVariant, w, h, S);
+    (void)w;
+    (void)h;
+    return final_ccl_lds<1, 4>(S) <= (64u << 10);
 }
 
 hipError_t launch_assign_final_ccl(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                   int64_t t, hipStream_t s) {
     if (!assign_final_ccl_supported(w, h, g.S)) return hipErrorInvalidValue;
-    const AssignImage a = assign_image(ws, w, h, g, kFinalCclVariant);
+    AssignImage a = assign_image(ws, w, h, g, 1);
+    a.tiles_x = (w + tile_ccl::kTile - 1) / tile_ccl::kTile;
     const AssignCcl cc{ws.ccl0, ws.ccl3, ws.ccl1};  // as the connectivity pass names them
-    return g.dist ? launch_final_ccl<1>(a, t, cc, g.S, s) : launch_final_ccl<0>(a, t, cc, g.S, s);
+    if (final_ccl_vec4(w, h, g.S))
+        return g.dist ? launch_final_ccl<4, 1, 1>(a, t, cc, g.S, s)
+                      : launch_final_ccl<4, 1, 0>(a, t, cc, g.S, s);
+    return g.dist ? launch_final_ccl<1, 4, 1>(a, t, cc, g.S, s)
+                  : launch_final_ccl<1, 4, 0>(a, t, cc, g.S, s);
 }
 
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,

@@ -87,3 +87,21 @@ def test_fused_segment_equals_separate_passes(slic, name):
     assert torch.equal(one["labels"], ctx.labels())
     assert int(one["n_segments"].cpu()[0]) == int(n.cpu()[0])
     ctx.close()
+
+
+@pytest.mark.parametrize("w,h,S,squared", [
+    (96, 70, 8, False),    # four pixels of a row per thread (S and width multiples of 4)
+    (128, 64, 16, True),
+    (98, 70, 8, False),    # width not a multiple of 4: one pixel in each of four rows
+    (96, 70, 6, False),    # step not a multiple of 4
+    (33, 97, 4, False),
+])
+def test_fused_segment_both_tile_shapes(slic, w, h, S, squared):
+    img = synth.voronoi_image(w * 131 + h, w, h, 9, 8.0)
+    print(f"case {w}x{h} S={S} squared={squared}", flush=True)
+    out = _segment(slic, img, S, 10.0, 3, 5, squared)
+    want = oracle.segment(img, S, 10.0, 3, True, True, 5,
+                          dist=oracle.DIST_SQUARED if squared else oracle.DIST_EQ1)
+    assert np.array_equal(out["labels"].cpu().numpy(), want["seg_labels"])
+    assert int(out["n_segments"].cpu()[0]) == want["n_segments"]
+    assert np.array_equal(out["centres"].cpu().numpy(), want["centres"])
