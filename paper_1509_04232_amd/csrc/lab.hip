@@ -91,19 +91,46 @@ __device__ __forceinline__ double newton_cbrt(double t) {
     return c * scale;
 }
 
+// The float that newton_cbrt(t) rounds to, for t in (216/24389, 1.1]: a
+// cheaper estimate c of the cube root (the inverse cube root seeded by the
+// hardware base-2 logarithm and exponential in FP32, then two Newton steps
+// in FP64; both c and newton_cbrt lie within about 2^-49 of the exact root)
+// is kept where it lies farther than 2^-40 (relative) from both midpoints
+// between its FP32 rounding and the neighbouring floats, since newton_cbrt
+// then rounds to the same float; elsewhere (about one value in 2^15)
+// newton_cbrt runs.
+__device__ __forceinline__ float cbrt_rounded(double td) {
+    const float tf = static_cast<float>(td);
+    const float z0 = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(tf) * (-1.0f / 3.0f));
+    double z = static_cast<double>(z0);
+    const double third = 1.0 / 3.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double z2 = z * z;
+        const double z3 = z2 * z;
+        const double err = __builtin_fma(-td, z3, 1.0);
+        const double corr = z * err;
+        z = __builtin_fma(corr, third, z);
+    }
+    double c = td * z;
+    c = c * z;
+    const float cf = static_cast<float>(c);
+    const double fc = static_cast<double>(cf);
+    const double up = static_cast<double>(__int_as_float(__float_as_int(cf) + 1));
+    const double dn = static_cast<double>(__int_as_float(__float_as_int(cf) - 1));
+    const double margin = c * 0x1p-40;
+    if (c < 0.5 * (fc + up) - margin && c > 0.5 * (fc + dn) + margin) return cf;
+    return static_cast<float>(newton_cbrt(td));
+}
+
 __device__ __forceinline__ float cie_f(float t) {
     const double td = static_cast<double>(t);
     const double eps = 216.0 / 24389.0;
     const double kappa = 24389.0 / 27.0;
-    double r;
-    if (td > eps) {
-        r = newton_cbrt(td);
-    } else {
-        const double p = kappa * td;
-        const double s = p + 16.0;
-        r = s / 116.0;
-    }
-    return static_cast<float>(r);
+    if (td > eps) return cbrt_rounded(td);
+    const double p = kappa * td;
+    const double s = p + 16.0;
+    return static_cast<float>(s / 116.0);
 }
 
 __device__ __forceinline__ void rgb_to_lab(const float* lin, const float* nm, const uint8_t* p,
