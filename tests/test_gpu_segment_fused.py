@@ -95,6 +95,8 @@ def test_fused_segment_equals_separate_passes(slic, name):
     (98, 70, 8, False),    # width not a multiple of 4: one pixel in each of four rows
     (96, 70, 6, False),    # step not a multiple of 4
     (33, 97, 4, False),
+    (200, 150, 64, False),  # cells larger than the 32 x 32 tiles
+    (70, 45, 1, False),     # S = 1: the window does not fit, the separate pass runs
 ])
 def test_fused_segment_both_tile_shapes(slic, w, h, S, squared):
     img = synth.voronoi_image(w * 131 + h, w, h, 9, 8.0)
