@@ -8,7 +8,9 @@
 // linear segment below), then L = 116 fy - 16, a = 500 (fx - fy),
 // b = 200 (fy - fz) in FP32.  Every operation is IEEE round-to-nearest in
 // the order written; the file is compiled without FMA contraction (the cube
-// root's fused multiply-adds are explicit).  The colour-space option yields
+// root's fused multiply-adds are explicit).  The cube root's result is that
+// of Newton's method as written below (newton_cbrt), rounded to FP32, reached
+// by a certified cheaper estimate wherever that provably rounds the same.  The colour-space option yields
 // XYZ scaled by 100 (same order, then the scaling) or the R, G, B bytes as
 // floats instead; the seeds and the gradient work on whichever planes.
 //
