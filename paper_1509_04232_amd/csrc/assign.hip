@@ -568,7 +568,10 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         }
     }
 
-    // ---- labels, then runs of equal cells into the LDS bins
+    // ---- labels, then runs of equal cells into the LDS bins (the last
+    // launch before the connectivity clean-up only stores the labels: no
+    // update follows it)
+    constexpr bool kSums = MODE != kModeFinalCcl;
     const float scale = static_cast<float>(1 << kQShift);
     int run_cell = -1;
     int rl = 0, ra = 0, rb = 0;
@@ -586,6 +589,7 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         } else {
             labels[pi] = kidx[cellv[r][0]];
         }
+        if constexpr (!kSums) continue;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int cell = cellv[r][v];
@@ -610,33 +614,35 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
             }
         }
     }
-    if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
-    __syncthreads();
-    if constexpr (kConv) {
-        if (threadIdx.x == 0 && s_shift)
-            atomicAdd(reinterpret_cast<unsigned long long*>(cv.ctl + t % 3), s_shift);
-    }
+    if constexpr (kSums) {
+        if (run_cell >= 0) add_bin(bins, ncells, run_cell, rl, ra, rb, rxyc);
+        __syncthreads();
+        if constexpr (kConv) {
+            if (threadIdx.x == 0 && s_shift)
+                atomicAdd(reinterpret_cast<unsigned long long*>(cv.ctl + t % 3), s_shift);
+        }
 
-    // ---- add the workgroup's bins to the global sums
-    for (int i = threadIdx.x; i < ncells; i += kThreads) {
-        const unsigned long long p = bins[3 * ncells + i];
-        const long long n = static_cast<long long>(p >> 40);
-        if (n == 0) continue;
-        const long long sx = static_cast<long long>(p & 0xFFFFFull) + n * x0;
-        const long long sy = static_cast<long long>((p >> 20) & 0xFFFFFull) + n * y0;
-        gmem<unsigned long long>* s = reinterpret_cast<gmem<unsigned long long>*>(
-            sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
-        const unsigned long long add[kSumStride] = {
-            bins[i], bins[ncells + i], bins[2 * ncells + i], static_cast<unsigned long long>(sx),
-            static_cast<unsigned long long>(sy), static_cast<unsigned long long>(n)};
+        // ---- add the workgroup's bins to the global sums
+        for (int i = threadIdx.x; i < ncells; i += kThreads) {
+            const unsigned long long p = bins[3 * ncells + i];
+            const long long n = static_cast<long long>(p >> 40);
+            if (n == 0) continue;
+            const long long sx = static_cast<long long>(p & 0xFFFFFull) + n * x0;
+            const long long sy = static_cast<long long>((p >> 20) & 0xFFFFFull) + n * y0;
+            gmem<unsigned long long>* s = reinterpret_cast<gmem<unsigned long long>*>(
+                sums_acc + static_cast<size_t>(kidx[i]) * kSumStride);
+            const unsigned long long add[kSumStride] = {
+                bins[i], bins[ncells + i], bins[2 * ncells + i],
+                static_cast<unsigned long long>(sx), static_cast<unsigned long long>(sy),
+                static_cast<unsigned long long>(n)};
 #pragma unroll
-        for (int j = 0; j < kSumStride; ++j)
-            __hip_atomic_fetch_add(s + j, add[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int j = 0; j < kSumStride; ++j)
+                __hip_atomic_fetch_add(s + j, add[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 
     // ---- the tile-local components of the labels just written (the
-    // connectivity pass's first step, on the same 32 x 32 tile), after the
-    // global adds are issued
+    // connectivity pass's first step, on the same 32 x 32 tile)
     if constexpr (MODE == kModeFinalCcl) {
         static_assert(Sh::kTileW == tile_ccl::kTile && Sh::kTileH == tile_ccl::kTile &&
                           kThreads == tile_ccl::kBlock,
