@@ -53,10 +53,11 @@ ASSIGN_SRC = os.path.join(ROOT, "paper_1509_04232_amd", "csrc", "assign.hip")
 
 
 def assign_bytes(n_pixels: int, n_clusters: int) -> int:
-    """Algorithmic bytes of one association launch: read Lab (12 B/pixel),
-    write the label (4 B/pixel), read each centre (20 B) and add its five
-    sums and count (48 B)."""
-    return 16 * n_pixels + 68 * n_clusters
+    """Algorithmic bytes of one association launch that another association
+    follows (every launch these timings measure): read Lab (12 B/pixel),
+    read each centre (20 B) and add its five sums and count (48 B).  The
+    labels (4 B/pixel more) are written by the last launch of a frame only."""
+    return 12 * n_pixels + 68 * n_clusters
 
 
 class Frame:

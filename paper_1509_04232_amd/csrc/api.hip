@@ -175,33 +175,36 @@ int check_buffers(const void* rgb, const void* ws) {
 // Association launch c->t.  With ccl set and *ccl true (the last launch
 // before the connectivity clean-up), the launch that also finds the
 // tile-local components where the image allows its shape; *ccl then says
-// whether it did.
-hipError_t associate(slic_ctx* c, bool* ccl) {
+// whether it did.  store: whether the labels are written (a launch that
+// another association follows before anything reads them skips them).
+hipError_t associate(slic_ctx* c, bool* ccl, bool store) {
     const slic_params& p = c->p;
     if (ccl && *ccl && !assign_final_ccl_supported(p.width, p.height, c->g.S)) *ccl = false;
     if (ccl && *ccl) return launch_assign_final_ccl(c->ws, p.width, p.height, c->g, c->t, c->stream);
-    return launch_assign(c->ws, p.width, p.height, c->g, c->t, c->variant, c->stream);
+    return launch_assign(c->ws, p.width, p.height, c->g, c->t, c->variant, c->stream, nullptr,
+                         store);
 }
 
-// Section 4's listing up to the first association (ccl: as in associate,
-// for a first association that is also the last).
-hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb, bool* ccl = nullptr) {
+// Section 4's listing up to the first association (ccl, store: as in
+// associate, for a first association that is also the last, or that rounds
+// follow at once).
+hipError_t enqueue_init(slic_ctx* c, const uint8_t* rgb, bool* ccl = nullptr, bool store = true) {
     const slic_params& p = c->p;
     hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
                                    (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
     if (e != hipSuccess) return e;
     c->t = 0;
-    e = associate(c, ccl);
+    e = associate(c, ccl, store);
     if (e == hipSuccess) c->t = 1;
     return e;
 }
 
 // n rounds of (update, associate): each association launch also completes
 // the previous launch's centre update (ccl: as in associate, for the last
-// of them; untouched when n is 0).
+// of them; untouched when n is 0).  Only the last launch writes the labels.
 hipError_t enqueue_iterations(slic_ctx* c, int32_t n, bool* ccl = nullptr) {
     for (int32_t i = 0; i < n; ++i) {
-        hipError_t e = associate(c, i == n - 1 ? ccl : nullptr);
+        hipError_t e = associate(c, i == n - 1 ? ccl : nullptr, i == n - 1);
         if (e != hipSuccess) return e;
         ++c->t;
     }
@@ -431,8 +434,9 @@ hipError_t batch_enqueue(const slic_batch* b, hipStream_t s) {
     const LabSeedTileMap lmap{b->lab_images, b->lab_tile_image, b->lab_tile_first};
     hipError_t e = launch_lab_seed_batch(lmap, b->lab_tiles, s);
     const AssignTileMap amap{b->asg_images, b->asg_tile_image, b->asg_tile_first};
-    for (int t = 0; e == hipSuccess && t <= b->n_iters; ++t)
-        e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, b->grids[0].dist, s);
+    for (int t = 0; e == hipSuccess && t <= b->n_iters; ++t)  // only the last writes labels
+        e = launch_assign_batch(amap, b->asg_tiles, b->min_S, t, b->variant, b->grids[0].dist, s,
+                                t == b->n_iters);
     if (e == hipSuccess && b->enforce && b->ccl_batched) {
         const CclMap cmap{b->ccl_images, b->ccl_tile_image, b->ccl_tile_first, b->ccl_blk_image,
                           b->ccl_blk_first};
@@ -483,7 +487,7 @@ int enqueue_segment(const slic_params* p, const uint8_t* d_rgb, int32_t n_iters,
     c.ws.labels = d_labels;  // associate straight into the caller's buffer
     // the last association also finds the tile-local components, if it can
     bool local_done = enforce != 0;
-    if (enqueue_init(&c, d_rgb, n_iters == 0 ? &local_done : nullptr) != hipSuccess)
+    if (enqueue_init(&c, d_rgb, n_iters == 0 ? &local_done : nullptr, n_iters == 0) != hipSuccess)
         return SLIC_EHIP;
     if (enqueue_iterations(&c, n_iters, &local_done) != hipSuccess) return SLIC_EHIP;
     if (d_energy &&
@@ -754,14 +758,17 @@ int slic_segment_noalloc(const slic_params* p, const uint8_t* d_rgb, int32_t n_i
 
 namespace {
 
-// slic_init with the net's decoded labels as the first association.
-hipError_t enqueue_warm_init(slic_ctx* c, const uint8_t* rgb, const void* d_net) {
+// slic_init with the net's decoded labels as the first association (store:
+// whether the decoded labels are written; rounds that follow at once make
+// them dead).
+hipError_t enqueue_warm_init(slic_ctx* c, const uint8_t* rgb, const void* d_net,
+                             bool store = true) {
     const slic_params& p = c->p;
     hipError_t e = launch_lab_seed(rgb, p.width, p.height, p.pitch, p.channels, c->ws, c->g,
                                    (p.flags & SLIC_PERTURB_SEEDS) ? 1 : 0, c->stream);
     if (e != hipSuccess) return e;
     c->t = 0;
-    e = launch_warm_start(c->ws, p.width, p.height, c->g, d_net, c->stream);
+    e = launch_warm_start(c->ws, p.width, p.height, c->g, d_net, c->stream, store);
     if (e == hipSuccess) c->t = 1;
     return e;
 }
@@ -819,7 +826,7 @@ int slic_warm_segment(const slic_params* p, const uint8_t* d_rgb, const void* d_
     slic_ctx c;
     bind(&c, p, d_ws, hip_stream);
     c.ws.labels = d_labels;
-    if (enqueue_warm_init(&c, d_rgb, d_net) != hipSuccess) return SLIC_EHIP;
+    if (enqueue_warm_init(&c, d_rgb, d_net, n_iters == 0) != hipSuccess) return SLIC_EHIP;
     // with rounds, the last association also finds the tile-local components
     bool local_done = enforce != 0 && n_iters > 0;
     if (enqueue_iterations(&c, n_iters, &local_done) != hipSuccess) return SLIC_EHIP;

@@ -229,7 +229,8 @@ using LaunchShape =
 // they need for latency hiding at large frames.
 template <int VEC, int ROWS, int DIST, int MODE>
 __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
-    AssignImage single, AssignTileMap map, long long t, Converge cv, AssignCcl cc) {
+    AssignImage single, AssignTileMap map, long long t, Converge cv, AssignCcl cc,
+    int store_labels) {
     using Sh = LaunchShape<VEC, ROWS, MODE>;
     constexpr bool kConv = MODE == kModeConverge;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -581,13 +582,15 @@ __global__ __launch_bounds__(kThreads, DIST == 0 ? 4 : 1) void assign_kernel(
         const int y = y0 + ty * ROWS + r;
         if (!col_ok || y >= g.h) continue;
         const size_t pi = static_cast<size_t>(y) * g.w + x;
-        if constexpr (VEC == 4) {
-            store_i4(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]],
-                     kidx[cellv[r][3]]);
-        } else if constexpr (VEC == 2) {
-            store_i2(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]]);
-        } else {
-            labels[pi] = kidx[cellv[r][0]];
+        if (store_labels) {
+            if constexpr (VEC == 4) {
+                store_i4(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]], kidx[cellv[r][2]],
+                         kidx[cellv[r][3]]);
+            } else if constexpr (VEC == 2) {
+                store_i2(labels + pi, kidx[cellv[r][0]], kidx[cellv[r][1]]);
+            } else {
+                labels[pi] = kidx[cellv[r][0]];
+            }
         }
         if constexpr (!kSums) continue;
 #pragma unroll
@@ -748,7 +751,8 @@ size_t variant_lds(int S) {
 
 template <int VEC, int ROWS, int DIST>
 hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int total_tiles,
-                          int min_S, long long t, const Converge& cv, hipStream_t s) {
+                          int min_S, long long t, const Converge& cv, bool store,
+                          hipStream_t s) {
     using Sh = Shape<VEC, ROWS>;
     dim3 grid;
     if (map.images) {
@@ -759,12 +763,14 @@ hipError_t launch_variant(const AssignImage& a, const AssignTileMap& map, int to
     KernelTimer timer("assign", s);
     const size_t lds = variant_lds<VEC, ROWS>(min_S);
     if (map.images) {
-        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv, {});
+        assign_kernel<VEC, ROWS, DIST, kModeBatch><<<grid, kThreads, lds, s>>>(a, map, t, cv, {},
+                                                                              store);
     } else if (cv.ctl) {
         assign_kernel<VEC, ROWS, DIST, kModeConverge><<<grid, kThreads, lds, s>>>(a, map, t, cv,
-                                                                                 {});
+                                                                                 {}, store);
     } else {
-        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv, {});
+        assign_kernel<VEC, ROWS, DIST, kModeSingle><<<grid, kThreads, lds, s>>>(a, map, t, cv, {},
+                                                                               store);
     }
     return hipGetLastError();
 }
@@ -788,7 +794,7 @@ hipError_t launch_final_ccl(const AssignImage& a, long long t, const AssignCcl& 
     const Converge off{nullptr, 0, 0};
     KernelTimer timer("assign", s);
     assign_kernel<VEC, ROWS, DIST, kModeFinalCcl><<<grid, kThreads, final_ccl_lds<VEC, ROWS>(S),
-                                                     s>>>(a, none, t, off, cc);
+                                                     s>>>(a, none, t, off, cc, 1);
     return hipGetLastError();
 }
 
@@ -798,7 +804,7 @@ bool final_ccl_vec4(int32_t w, int32_t h, int32_t S) {
 }
 
 using LaunchFn = hipError_t (*)(const AssignImage&, const AssignTileMap&, int, int, long long,
-                                const Converge&, hipStream_t);
+                                const Converge&, bool, hipStream_t);
 
 struct VariantDesc {
     int vec, rows;
@@ -885,12 +891,13 @@ AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& 
 }
 
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int variant, hipStream_t s, const Converge* cv) {
+                         int variant, hipStream_t s, const Converge* cv, bool store_labels) {
     if (!assign_variant_supported(variant, w, h, g.S)) variant = assign_default_variant(w, h, g.S);
     const AssignImage a = assign_image(ws, w, h, g, variant);
     const AssignTileMap none{nullptr, nullptr, nullptr};
     const Converge off{nullptr, 0, 0};
-    return kVariants[variant - 1].launch[g.dist ? 1 : 0](a, none, 0, g.S, t, cv ? *cv : off, s);
+    return kVariants[variant - 1].launch[g.dist ? 1 : 0](a, none, 0, g.S, t, cv ? *cv : off,
+                                                         store_labels, s);
 }
 
 bool assign_final_ccl_supported(int32_t w, int32_t h, int32_t S) {
@@ -913,11 +920,12 @@ hipError_t launch_assign_final_ccl(const Workspace& ws, int32_t w, int32_t h, co
 }
 
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
-                               int variant, int dist, hipStream_t s) {
+                               int variant, int dist, hipStream_t s, bool store_labels) {
     if (variant < 1 || variant > kNumVariants || !map.images) return hipErrorInvalidValue;
     AssignImage unused{};
     const Converge off{nullptr, 0, 0};
-    return kVariants[variant - 1].launch[dist ? 1 : 0](unused, map, total_tiles, min_S, t, off, s);
+    return kVariants[variant - 1].launch[dist ? 1 : 0](unused, map, total_tiles, min_S, t, off,
+                                                       store_labels, s);
 }
 
 hipError_t launch_energy(const Workspace& ws, int32_t w, int32_t h, const Grid& g, double* out,

@@ -580,7 +580,7 @@ struct FusedImage {
     int w, h, S, ns_c, ns_r;
     const float *b1, *b2, *b3, *P;
     const float* conf;  // minimum softmax probability of a voting pixel
-    int32_t* labels;
+    int32_t* labels;  // null: the decoded labels are not stored
     long long *sums_acc, *sums_next;
     int tiles_x, n_tiles;
 };
@@ -955,7 +955,7 @@ __global__ __launch_bounds__(kFT, kFPerCU) void net_fused_kernel(FusedImage g, N
             if (x < g.w && y < g.h) {
                 const int cy = min(max(tab[2 * kFW + dr] + bc / 3 - 1, 0), g.ns_r - 1);
                 const int cx = min(max(tab[dc] + bc % 3 - 1, 0), g.ns_c - 1);
-                g.labels[static_cast<size_t>(y) * g.w + x] = cy * g.ns_c + cx;
+                if (g.labels) g.labels[static_cast<size_t>(y) * g.w + x] = cy * g.ns_c + cx;
                 // the pixel votes in the first update when its best class's
                 // probability reaches the prepared minimum confidence
                 if (se * tau <= 1.0f) {
@@ -1210,7 +1210,7 @@ size_t prepared_layout(NetWeights* wt, float** params, char* base) {
 }
 
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
-                             const void* d_net, hipStream_t s) {
+                             const void* d_net, hipStream_t s, bool store_labels) {
     NetWeights wt;
     float* params;
     prepared_layout(&wt, &params, static_cast<char*>(const_cast<void*>(d_net)));
@@ -1219,7 +1219,8 @@ hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Gr
     const int n_tiles = tiles_x * ((h + kFH - 1) / kFH);
     FusedImage f{ws.L, ws.A, ws.B, w, h, g.S, g.ns_c, g.ns_r,
                  params + kOffB1, params + kOffB2, params + kOffB3, params + kOffP,
-                 params + kMaxParams, ws.labels, ws.sums, ws.sums + ring, tiles_x, n_tiles};
+                 params + kMaxParams, store_labels ? ws.labels : nullptr, ws.sums,
+                 ws.sums + ring, tiles_x, n_tiles};
     // persistent workgroups, kFPerCU per compute unit (their LDS fits that often)
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

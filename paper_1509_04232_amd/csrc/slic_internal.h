@@ -114,9 +114,12 @@ hipError_t launch_converge_result(const long long* ctl, int32_t max_iters, int32
 // Association launch number t (0: the first, with the seeds as centres;
 // t >= 1 also completes the centre update of the previous launch).
 // variant: launch shape 1..assign_variant_count(); an unsupported value
-// falls back to assign_default_variant.
+// falls back to assign_default_variant.  store_labels false: the labels are
+// not written (a launch that another association launch follows before
+// anything reads them).
 hipError_t launch_assign(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int64_t t,
-                         int variant, hipStream_t s, const Converge* cv = nullptr);
+                         int variant, hipStream_t s, const Converge* cv = nullptr,
+                         bool store_labels = true);
 // Association launch t as the last one before the connectivity clean-up:
 // it also writes the clean-up's tile-local components (ws.ccl0, ws.ccl3,
 // ws.ccl1, the connectivity pass's first step), so launch_connectivity then
@@ -126,7 +129,7 @@ bool assign_final_ccl_supported(int32_t w, int32_t h, int32_t S);
 hipError_t launch_assign_final_ccl(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
                                   int64_t t, hipStream_t s);
 hipError_t launch_assign_batch(const AssignTileMap& map, int total_tiles, int min_S, int64_t t,
-                               int variant, int dist, hipStream_t s);
+                               int variant, int dist, hipStream_t s, bool store_labels = true);
 AssignImage assign_image(const Workspace& ws, int32_t w, int32_t h, const Grid& g, int variant);
 bool assign_tiles(int variant, int32_t w, int32_t h, int* tiles_x, int* tiles_y);
 int assign_variant_count();
@@ -195,9 +198,11 @@ hipError_t launch_export_centres(const Workspace& ws, const Grid& g, float* out,
 
 // Learned warm start (net.hip).  warm_supported: the net handles step S.
 // launch_warm_start: after launch_lab_seed, runs the prepared net d_net on
-// ws.L/A/B, writes the decoded labels to ws.labels, accumulates them into
-// the first accumulator buffer (as association launch 0 would) and clears
-// the second, so that association launch 1 starts from the net's labels.
+// ws.L/A/B, writes the decoded labels to ws.labels (unless store_labels is
+// false: association rounds follow before anything reads them), accumulates
+// them into the first accumulator buffer (as association launch 0 would)
+// and clears the second, so that association launch 1 starts from the
+// net's labels.
 bool warm_supported(int32_t S);
 // slic_net_prepare records the step S each prepared buffer holds (per
 // device and address); prepared_step returns it, 0 for a buffer it never
@@ -205,7 +210,7 @@ bool warm_supported(int32_t S);
 void record_prepared(const void* d_net, int32_t S);
 int32_t prepared_step(const void* d_net);
 hipError_t launch_warm_start(const Workspace& ws, int32_t w, int32_t h, const Grid& g,
-                             const void* d_net, hipStream_t s);
+                             const void* d_net, hipStream_t s, bool store_labels = true);
 
 // Kernel timing: while enabled, a KernelTimer brackets a launch with HIP
 // events on the launch stream.
