@@ -107,3 +107,20 @@ def test_fused_segment_both_tile_shapes(slic, w, h, S, squared):
     assert np.array_equal(out["labels"].cpu().numpy(), want["seg_labels"])
     assert int(out["n_segments"].cpu()[0]) == want["n_segments"]
     assert np.array_equal(out["centres"].cpu().numpy(), want["centres"])
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 5])
+def test_one_call_labels_without_connectivity(slic, iters):
+    """Only the last association launch of a one-call segmentation writes
+    labels: the labels and centres after 0..5 rounds without the clean-up
+    equal the oracle's."""
+    w, h, S = 150, 90, 8
+    img = synth.voronoi_image(77 + iters, w, h, 12, 8.0)
+    p = slic.Params(w, h, S=S, m=10.0)
+    rgb = torch.from_numpy(np.ascontiguousarray(img).reshape(-1)).cuda()
+    print(f"case iters={iters}", flush=True)
+    out = slic.segment(rgb, p, iters, enforce=False, want_centres=True)
+    torch.cuda.synchronize()
+    want = oracle.segment(img, S, 10.0, iters, True)
+    assert np.array_equal(out["labels"].cpu().numpy(), want["labels"])
+    assert np.array_equal(out["centres"].cpu().numpy(), want["centres"])
