@@ -207,6 +207,35 @@ def test_warm_segment_matches_oracle(slic, w, h, S, perturb, iters):
     assert float(out["energy"].cpu()[0]) == pytest.approx(energy, rel=1e-9)
 
 
+@pytest.mark.parametrize("w,h,S,perturb,iters", [
+    (97, 61, 8, True, 2), (130, 77, 5, False, 3), (64, 64, 16, True, 1), (150, 90, 8, True, 0),
+    (70, 45, 2, True, 2)])
+def test_warm_segment_with_connectivity_matches_oracle(slic, w, h, S, perturb, iters):
+    """The warm start with the clean-up: with rounds its last association
+    also finds the tile-local components; the labels after the clean-up
+    equal the oracle's connectivity step on the oracle's composition."""
+    img, lab = _image(w, h, 40 + S)
+    p = _decisive_params(S, 50 + w)
+    lg, _, _ = oracle.net_forward(lab, p.astype(np.float64), S, True)
+    top2 = np.sort(lg, axis=-1)[..., -2:]
+    assert (top2[..., 1] - top2[..., 0]).min() > 1.0
+    labels = oracle.net_decode(lg, S)
+    cen = oracle.seed(lab, S, perturb)
+    for _ in range(iters):
+        cen, _ = oracle.update(lab, labels, cen)
+        labels = oracle.assign(lab, S, 10.0, cen)
+    seg, n_seg, _ = oracle.connectivity(labels, S, 0)
+
+    prm = slic.Params(w, h, S=S, m=10.0, perturb=perturb)
+    net = slic.warm.prepare(_dev(p), S)
+    out = slic.warm.warm_segment(_dev(img.reshape(-1)), prm, net, iters, enforce=True,
+                                 want_centres=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["labels"].cpu().numpy(), seg)
+    assert int(out["n_segments"].cpu()[0]) == n_seg
+    assert np.array_equal(out["centres"].cpu().numpy(), cen)
+
+
 def _two_level_params(S, seed):
     """Like _decisive_params, but at every other phase the leading class is
     only 2.5 above the rest: those pixels' best class is far less probable,
